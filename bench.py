@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of rpCholesky-QR on one MI355X.
+
+One step = one full factorization (sample, gather, sketch QR, pass A, Gram
+reduction, Cholesky, R product, pass B) of the 1,000,000 x 64 workload with
+s = 3n = 192 sampled rows: A = U diag(sigma) V^T, kappa = 1e8, seed 0, FP64,
+resident in HBM before the timed region starts.
+
+value = algorithmic bytes per factorization (24 m n: A read twice, Q written
+once) / time per factorization, in GB/s; factorizations/s is reported beside it.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rpCholQR GB/s & factorizations/s; mixed/batched vs FP64 at orth err<=1e-12"
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFS = 78.6       # MI355X FP64 (vector and matrix share this rate)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--m", type=int, default=1_000_000)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--s", type=int, default=None)
+    ap.add_argument("--kappa", type=float, default=1e8)
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the per-kappa accuracy sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=2)
+    return ap.parse_args()
+
+
+def host_cores() -> int:
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(row sharding over several GPUs is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2406_11751_amd as rq
+    from workloads import gen_usv, metrics
+
+    m, n = args.m, args.n
+    s = args.s or 3 * n
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bytes_alg = 24.0 * m * n            # A read twice + Q written once
+    flops_alg = 3.0 * m * n * n         # TRSM (m n^2) + SYRK (m n (n+1)) + TRSM (m n^2), to leading order
+
+    def to_dev(A_h):
+        return torch.from_numpy(np.ascontiguousarray(A_h.T)).to(dev).t()
+
+    t0 = time.time()
+    A_h = gen_usv(m, n, args.kappa, 0)
+    A = to_dev(A_h)
+    print(f"# input {m}x{n} kappa={args.kappa:.0e} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    Q = rq.colmajor_empty(m, n, dev)
+    R = rq.colmajor_empty(n, n, dev)
+    ws = torch.empty(rq.workspace_bytes(m, n, s), dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+
+    def step():
+        rq.factor(A, s, 0, Q=Q, R=R, workspace=ws, info=info, check=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, -1], info
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # Per-kernel durations: HIP events recorded by the library between its kernels on
+    # the same stream, over a second timed loop of the same length.
+    rq.timing_enable(True)
+    for _ in range(args.steps):
+        step()
+    calls, stage_ms = rq.timing_read()
+    rq.timing_enable(False)
+    stage_avg = {k: v / calls for k, v in stage_ms.items()}
+    print(f"# {ms * 1e3:.1f} us/factorization; stages (us): "
+          + " ".join(f"{k}={v * 1e3:.1f}" for k, v in stage_avg.items()), file=sys.stderr, flush=True)
+
+    # Accuracy of this run and of the kappa sweep (the metric is quoted at orth <= 1e-12).
+    acc = {}
+    Qh_orth = metrics.orth_error(Q)
+    acc[f"{args.kappa:.0e}"] = dict(orth=Qh_orth, residual=metrics.residual(A, Q, R))
+    if not args.no_accuracy:
+        for kappa in (1.0, 1e4, 1e12, 1e15):
+            Ak = to_dev(gen_usv(m, n, kappa, 0))
+            Qk, Rk, _ = rq.factor(Ak, s, 0)
+            acc[f"{kappa:.0e}"] = dict(orth=metrics.orth_error(Qk), residual=metrics.residual(Ak, Qk, Rk))
+            del Ak, Qk, Rk
+    print("# accuracy " + json.dumps(acc), file=sys.stderr, flush=True)
+
+    pa_us, pb_us = stage_avg["passA"] * 1e3, stage_avg["passB"] * 1e3
+    # pass B moves 16 m n bytes (read A, write Q); pass A performs m n^2 + m n (n + 1) flops.
+    passB_gbs = 16.0 * m * n / (pb_us * 1e-6) / 1e9
+    passA_tfs = (m * n * n + m * n * (n + 1)) * 1.0 / (pa_us * 1e-6) / 1e12
+    dominant = "passB" if pb_us >= pa_us else "passA"
+    if dominant == "passB":
+        roofline = dict(kernel="k_passB", bound="hbm", achieved=passB_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=passB_gbs / HBM_PEAK_GBS, traffic=None)
+    else:
+        roofline = dict(kernel="k_passA_mfma", bound="mfma", achieved=passA_tfs, peak=FP64_PEAK_TFS,
+                        unit="TFLOP/s", frac=passA_tfs / FP64_PEAK_TFS, traffic=None)
+    t_roof = max(8.0 * m * n / (HBM_PEAK_GBS * 1e9), (m * n * n + m * n * (n + 1)) / (FP64_PEAK_TFS * 1e12)) + \
+        max(16.0 * m * n / (HBM_PEAK_GBS * 1e9), 2.0 * m * n * n / (FP64_PEAK_TFS * 1e12))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        cores = host_cores()
+        runs = max(1, args.cpu_runs)
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            r = oracle.rpcholqr(A_h, s, 0, nthreads=cores, keep=True)
+        dt = (time.perf_counter() - t0) / runs
+        assert r.status == oracle.OK
+        cpu = dict(value=bytes_alg / dt / 1e9, unit="GB/s", cores=cores, kind="oracle",
+                   factorizations_per_s=1.0 / dt, seconds_per_factorization=dt,
+                   sample=f"{runs} full oracle factorization(s) of the same {m}x{n} input, s={s}")
+
+    out = {
+        "metric": METRIC,
+        "value": bytes_alg / (ms * 1e-3) / 1e9,
+        "unit": "GB/s",
+        "factorizations_per_s": 1e3 / ms,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"rpCholesky-QR FP64, A {m}x{n} = U diag(sigma) V^T, kappa={args.kappa:.0e}, "
+                               f"s={s} sampled rows, seed 0", "m": m, "n": n, "s": s, "kappa": args.kappa,
+                   "parallelism": "single GPU"},
+        "gflops": flops_alg / (ms * 1e-3) / 1e9,
+        "stage_us": {k: v * 1e3 for k, v in stage_avg.items()},
+        "roofline": roofline,
+        "roofline_whole_path": dict(t_roof_us=t_roof * 1e6, frac=t_roof / (ms * 1e-3),
+                                    model="sum over passes of max(bytes/8 TB/s, flops/78.6 TF)"),
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,135 @@
+/*
+ * rpcholqr.h -- C ABI of the MI355X (gfx950) library for randomized
+ * preconditioned Cholesky-QR (rpCholesky-QR), Garrison & Ipsen,
+ * "A randomized preconditioned Cholesky-QR algorithm", arXiv 2406.11751.
+ *
+ * Problem (Section 1; Section 2.1): given A in R^{m x n} with rank n and
+ * m >= n, compute a thin QR factorization A = Q R with Q^T Q = I_n and R upper
+ * triangular, nonsingular, with a positive diagonal (the factorization with a
+ * positive diagonal is unique, Lemma l_r1r2).
+ *
+ * Method (Algorithm rpCholesky-QR, Section 4), with the smoothing matrix F = I:
+ *   1. sample s >= n row indices uniformly, independently, with replacement,
+ *      from `seed` (SplitMix64 output r, reduced to [0, m) by a 64x64->128 bit
+ *      multiply-high; 0-based);
+ *   2. A_s = sqrt(m/s) * A(idx, :)  (scale of the paper's Remark r_exp);
+ *   3. Householder QR of A_s, keep R_s (diagonal made positive);
+ *   4. A1 = A R_s^{-1} by row-wise substitution;
+ *   5. G1 = A1^T A1;  6. G1 = R2^T R2 (Cholesky);  7. Q = A1 R2^{-1};
+ *   8. R = R2 R_s.
+ * Steps 4-8 are Algorithm "Preconditioned Cholesky-QR" (Section 3.1).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are IEEE binary64, column-major: element (i, j) of a matrix with
+ *    leading dimension ld is at [i + j*ld].
+ *  - Matrix and workspace pointers are DEVICE pointers (HIP device memory on
+ *    the current device); `stream` is a hipStream_t passed as void* (NULL = the
+ *    default stream).  The caller owns every buffer; the library never frees
+ *    caller memory.
+ *  - Calls are asynchronous and stream-ordered.  The return value reports only
+ *    argument and launch problems (rpcholqr_status).  Numerical failures are
+ *    written to the device rpcholqr_info the caller passes; read it after
+ *    synchronizing the stream.  On a numerical failure Q and R are unspecified.
+ *  - A is read only.  Q must not overlap A (A is read twice), R must not
+ *    overlap A or Q.  The strictly lower triangle of R is written as zero.
+ */
+#ifndef RPCHOLQR_H
+#define RPCHOLQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Synchronous status returned by every call. */
+typedef enum {
+  RPCHOLQR_OK = 0,
+  RPCHOLQR_EINVAL = -1,      /* n < 1, m < n, s < n, ld* too small, NULL or overlapping buffers */
+  RPCHOLQR_EHIP = -2,        /* a HIP runtime call or kernel launch failed */
+  RPCHOLQR_EWORKSPACE = -3,  /* workspace NULL or smaller than rpcholqr_workspace_bytes() */
+  RPCHOLQR_EUNSUPPORTED = -4 /* n or s beyond what this build supports (rpcholqr_max_n()) */
+} rpcholqr_status;
+
+/* Arithmetic of the passes over A.  Only RPCHOLQR_FP64 is available in this
+ * version; the others return RPCHOLQR_EUNSUPPORTED. */
+typedef enum {
+  RPCHOLQR_FP64 = 0,
+  RPCHOLQR_FP32_REFINE = 1,
+  RPCHOLQR_BF16X2_REFINE = 2
+} rpcholqr_precision;
+
+/* Numerical outcome, written on the device by the library. */
+typedef struct {
+  int32_t code;  /* RPCHOLQR_INFO_* */
+  int32_t index; /* 0-based failing column, -1 when code == RPCHOLQR_INFO_OK */
+} rpcholqr_info;
+
+#define RPCHOLQR_INFO_OK 0
+/* Sketch QR (step 3): a Householder column norm of A_s is zero or not finite. */
+#define RPCHOLQR_INFO_ESKETCH 1
+/* Cholesky of G1 (step 6): a pivot is not positive or not finite (the
+ * hypothesis kappa(A1)^2 gamma_2 < 1 of Theorem t_perturb2 failed). */
+#define RPCHOLQR_INFO_ECHOL 2
+
+/* Largest n this build accepts. */
+int32_t rpcholqr_max_n(void);
+
+/* Device workspace in bytes needed by rpcholqr_factor / rpcholqr_factor_debug
+ * for these sizes (0 if the sizes are invalid or unsupported). */
+size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision);
+
+/* Thin QR A = Q R by rpCholesky-QR (Algorithm rpCholesky-QR, Section 4).
+ *   m, n, s     rows, columns, sampled rows (1 <= n <= m, n <= s)
+ *   seed        seed of the sampled row indices
+ *   A, lda      input, m x n, lda >= m (device, read only)
+ *   Q, ldq      output, m x n, ldq >= m (device)
+ *   R, ldr      output, n x n upper triangular, ldr >= n (device)
+ *   precision   rpcholqr_precision
+ *   workspace   device scratch of at least rpcholqr_workspace_bytes() bytes,
+ *               256-byte aligned; contents on entry are ignored
+ *   info        device rpcholqr_info receiving the numerical outcome
+ *   stream      hipStream_t as void*
+ * The result is deterministic: the same inputs give the same bits. */
+int32_t rpcholqr_factor(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
+                        double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
+                        void* workspace, size_t workspace_bytes, rpcholqr_info* info, void* stream);
+
+/* rpcholqr_factor plus copies of the intermediates, for checking each step.
+ * Every extra pointer is a device pointer and may be NULL (not written):
+ *   idx  int64[s]              sampled row indices (step 1)
+ *   As   s x n, ld s           scaled sample (step 2)
+ *   Rs   n x n, ld n           sketch factor R_s, positive diagonal (step 3)
+ *   A1   m x n, ld m           preconditioned matrix A R_s^{-1} (step 4)
+ *   G1   n x n, ld n           Gram matrix, upper triangle (step 5)
+ *   R2   n x n, ld n           Cholesky factor of G1 (step 6)
+ * The workspace requirement is the same as for rpcholqr_factor. */
+int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A,
+                              int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
+                              int32_t precision, void* workspace, size_t workspace_bytes,
+                              rpcholqr_info* info, void* stream, int64_t* idx, double* As, double* Rs,
+                              double* A1, double* G1, double* R2);
+
+/* Per-kernel timing with HIP events, for measurement.  While enabled, every
+ * factor call records an event on its stream before the first kernel and after
+ * each of its NSTAGES kernels (in order: sketch = sample + gather + sketch QR,
+ * pass A = A1 and Gram partials, reduce = partial Gram sum, cholesky =
+ * Cholesky + R product, pass B = A1 again and Q).  No device memory is
+ * allocated.  Process-wide state: do not time calls from several host threads
+ * at once.
+ *   rpcholqr_timing_enable(1) starts recording (and discards earlier records),
+ *   rpcholqr_timing_enable(0) stops it; returns RPCHOLQR_OK or RPCHOLQR_EHIP.
+ *   rpcholqr_timing_read(ms, count) waits for the recorded events, writes into
+ *   ms[i] (host array of `count` doubles) the summed milliseconds of stage i
+ *   over all calls recorded since the last read, clears the records, and
+ *   returns the number of calls summed (negative rpcholqr_status on error). */
+#define RPCHOLQR_NSTAGES 5
+int32_t rpcholqr_timing_enable(int32_t on);
+int32_t rpcholqr_timing_read(double* ms, int32_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCHOLQR_H */

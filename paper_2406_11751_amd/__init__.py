@@ -1,0 +1,8 @@
+"""MI355X (gfx950) library for randomized preconditioned Cholesky-QR.
+
+Garrison & Ipsen, "A randomized preconditioned Cholesky-QR algorithm"
+(arXiv 2406.11751).  The computation lives in HIP kernels behind the C ABI of
+include/rpcholqr.h; this package only builds and binds that library.
+"""
+from .native import (FP64, FP32_REFINE, BF16X2_REFINE, RpCholQRError, colmajor_empty, factor,  # noqa: F401
+                     load_library, max_n, timing_enable, timing_read, workspace_bytes)

@@ -1,0 +1,154 @@
+"""ctypes binding of the C ABI declared in include/rpcholqr.h.
+
+Argument marshalling only: every step of the factorization runs in the HIP
+kernels of librpcholqr.so.  torch supplies device memory and the stream.
+Matrices are float64 CUDA (HIP) tensors in column-major order, i.e. an (m, n)
+tensor with strides (1, ld), ld >= m -- for example ``torch.empty(n, m).t()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "librpcholqr.so")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "EWORKSPACE", -4: "EUNSUPPORTED"}
+INFO = {0: "OK", 1: "ESKETCH", 2: "ECHOL"}
+FP64, FP32_REFINE, BF16X2_REFINE = 0, 1, 2
+
+# Every function the header declares, with its ctypes signature.
+_i64, _u64, _i32, _vp, _sz = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+SIGNATURES = {
+    "rpcholqr_max_n": (_i32, []),
+    "rpcholqr_workspace_bytes": (_sz, [_i64, _i64, _i64, _i32]),
+    "rpcholqr_factor": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz, _vp, _vp]),
+    "rpcholqr_factor_debug": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz,
+                                     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rpcholqr_timing_enable": (_i32, [_i32]),
+    "rpcholqr_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), _i32]),
+}
+NSTAGES = 5
+STAGES = ("sketch", "passA", "reduce", "cholesky", "passB")
+
+
+class RpCholQRError(RuntimeError):
+    """A call returned a non-OK status, or the device reported a numerical failure."""
+
+    def __init__(self, msg, status=None, code=None, index=None):
+        super().__init__(msg)
+        self.status, self.code, self.index = status, code, index
+
+
+_lib = None
+
+
+def load_library():
+    """Loads librpcholqr.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2406_11751_amd.build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def max_n() -> int:
+    return int(load_library().rpcholqr_max_n())
+
+
+def workspace_bytes(m: int, n: int, s: int, precision: int = FP64) -> int:
+    return int(load_library().rpcholqr_workspace_bytes(m, n, s, precision))
+
+
+def timing_enable(on: bool = True) -> None:
+    rc = load_library().rpcholqr_timing_enable(1 if on else 0)
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_timing_enable returned {STATUS.get(rc, rc)}", status=rc)
+
+
+def timing_read():
+    """(calls, {stage: summed ms}) of the calls timed since the last read."""
+    buf = (ctypes.c_double * NSTAGES)()
+    calls = load_library().rpcholqr_timing_read(buf, NSTAGES)
+    if calls < 0:
+        raise RpCholQRError(f"rpcholqr_timing_read returned {STATUS.get(calls, calls)}", status=calls)
+    return calls, {STAGES[i]: buf[i] for i in range(NSTAGES)}
+
+
+def colmajor_empty(m: int, n: int, device, dtype=None):
+    """Uninitialized (m, n) column-major tensor with leading dimension m."""
+    import torch
+
+    return torch.empty((n, m), dtype=dtype or torch.float64, device=device).t()
+
+
+def _ld(t, rows):
+    import torch
+
+    if t.dtype != torch.float64 or t.dim() != 2 or not t.is_cuda:
+        raise ValueError("expected a 2-D float64 device tensor")
+    if t.shape[0] != rows:
+        raise ValueError(f"expected {rows} rows, got {t.shape[0]}")
+    if t.shape[1] > 1 and t.stride(0) != 1:
+        raise ValueError("matrix must be column-major (stride (1, ld))")
+    return max(t.stride(1), rows) if t.shape[1] > 1 else max(rows, 1)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, stream=None,
+           precision: int = FP64, check: bool = True, debug: bool = False):
+    """Thin QR A = Q R by rpCholesky-QR on the GPU.
+
+    Returns (Q, R, info) where info is a device int32 tensor {code, index}.
+    With check=True the stream is synchronized and a numerical failure raises
+    RpCholQRError.  With debug=True a dict of intermediates (idx, As, Rs, A1,
+    G1, R2) is returned as a fourth element.
+    """
+    import torch
+
+    lib = load_library()
+    m, n = A.shape
+    dev = A.device
+    lda = _ld(A, m)
+    if Q is None:
+        Q = colmajor_empty(m, n, dev)
+    if R is None:
+        R = colmajor_empty(n, n, dev)
+    ldq, ldr = _ld(Q, m), _ld(R, n)
+    wsb = workspace_bytes(m, n, s, precision)
+    if wsb == 0:
+        raise RpCholQRError(f"unsupported sizes m={m} n={n} s={s} (max n {max_n()})", status=-4)
+    if workspace is None or workspace.numel() * workspace.element_size() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if info is None:
+        info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)
+    common = (m, n, s, seed & (2**64 - 1), _ptr(A), lda, _ptr(Q), ldq, _ptr(R), ldr, precision,
+              _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(info), st)
+    extra = None
+    if debug:
+        extra = dict(idx=torch.empty(s, dtype=torch.int64, device=dev), As=colmajor_empty(s, n, dev),
+                     Rs=colmajor_empty(n, n, dev), A1=colmajor_empty(m, n, dev),
+                     G1=colmajor_empty(n, n, dev), R2=colmajor_empty(n, n, dev))
+        rc = lib.rpcholqr_factor_debug(*common, *(_ptr(extra[k]) for k in ("idx", "As", "Rs", "A1", "G1", "R2")))
+    else:
+        rc = lib.rpcholqr_factor(*common)
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_factor returned {STATUS.get(rc, rc)}", status=rc)
+    if check:
+        torch.cuda.synchronize(dev)
+        code, index = (int(v) for v in info.cpu().tolist())
+        if code != 0:
+            raise RpCholQRError(f"numerical failure {INFO.get(code, code)} at column {index}", code=code,
+                                index=index)
+    return (Q, R, info, extra) if debug else (Q, R, info)

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every function include/rpcholqr.h declares.
+
+CPU only: no compute call is made (there may be no GPU here).
+"""
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "rpcholqr.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int32_t|size_t|void)\s+(rpcholqr_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for want in ("rpcholqr_factor", "rpcholqr_factor_debug", "rpcholqr_workspace_bytes", "rpcholqr_max_n",
+                 "rpcholqr_timing_enable", "rpcholqr_timing_read"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2406_11751_amd as rq
+    from paper_2406_11751_amd import native
+
+    lib = rq.load_library()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+        assert name in native.SIGNATURES, f"binding lacks {name}"
+
+
+def test_workspace_query_host_logic():
+    import paper_2406_11751_amd as rq
+
+    assert rq.max_n() >= 64
+    assert rq.workspace_bytes(10_000, 50, 150) > 0
+    assert rq.workspace_bytes(1_000_000, 64, 192) > 0
+    # invalid or unsupported sizes -> 0
+    assert rq.workspace_bytes(10, 20, 40) == 0       # m < n
+    assert rq.workspace_bytes(100, 10, 5) == 0       # s < n
+    assert rq.workspace_bytes(100, 0, 5) == 0        # n < 1
+    assert rq.workspace_bytes(1000, rq.max_n() + 1, 500) == 0
+    assert rq.workspace_bytes(100, 10, 30, precision=7) == 0
+    # the workspace grows with the generic sketch path (s > 512) by s*n doubles
+    small = rq.workspace_bytes(100_000, 32, 512)
+    big = rq.workspace_bytes(100_000, 32, 600)
+    assert big - small >= 600 * 32 * 8
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_2406_11751_amd import native
+
+    monkeypatch.setattr(native, "LIB_PATH", "/nonexistent/librpcholqr.so")
+    monkeypatch.setattr(native, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        native.load_library()
