@@ -32,8 +32,9 @@
  *  - The sample is scaled by sqrt(m/c) as in the paper's Matlab listing
  *    (Remark "r_exp", Section 5).
  *  - The thin QR of the sample is Householder QR with beta = -sign(alpha)*nu and
- *    dot products summed in a fixed 64-way interleaved order (CR64 below); the
- *    resulting R_s is then made to have a positive diagonal by flipping row signs.
+ *    dot products summed in a fixed 16-way interleaved order with a fixed
+ *    pairwise tree (CR16 below); the resulting R_s is then made to have a
+ *    positive diagonal by flipping row signs.
  *  - Triangular solves multiply by a correctly rounded reciprocal of the
  *    diagonal and accumulate with fma in ascending k.
  * Only these fixed orders make the result reproducible bit for bit by another
@@ -88,15 +89,16 @@ void orc_gather(int64_t m, int64_t n, int64_t s, const int64_t* idx, const doubl
  * Thin QR of the sample (Algorithm rpCholesky-QR line 3), R factor only.
  * ------------------------------------------------------------------------- */
 
-/* CR64: sum over rows r = k..len-1 of x[r]*y[r].  Row r is accumulated with
- * fma into partial p[r mod 64] in ascending r; the 64 partials are then added
- * pairwise, p[l] += p[l+h] for h = 32,16,8,4,2,1.  Returns p[0]. */
-static double cr64(const double* x, const double* y, int64_t k, int64_t len) {
-  double p[64];
-  for (int l = 0; l < 64; ++l) p[l] = 0.0;
-  for (int64_t r = k; r < len; ++r) p[r % 64] = fma(x[r], y[r], p[r % 64]);
-  for (int h = 32; h >= 1; h /= 2)
-    for (int l = 0; l < h; ++l) p[l] = p[l] + p[l + h];
+/* CR16: sum over rows r = k..len-1 of x[r]*y[r].  Row r is accumulated with
+ * fma into partial p[r mod 16] in ascending r; the 16 partials are then added
+ * as a pairwise tree: p[i] += p[i+h] for h = 1, 2, 4, 8 and i a multiple of 2h.
+ * Returns p[0]. */
+static double cr16(const double* x, const double* y, int64_t k, int64_t len) {
+  double p[16];
+  for (int l = 0; l < 16; ++l) p[l] = 0.0;
+  for (int64_t r = k; r < len; ++r) p[r % 16] = fma(x[r], y[r], p[r % 16]);
+  for (int h = 1; h < 16; h *= 2)
+    for (int i = 0; i < 16; i += 2 * h) p[i] = p[i] + p[i + h];
   return p[0];
 }
 
@@ -111,7 +113,7 @@ int orc_householder_r(int64_t s, int64_t n, double* W, int64_t ldw, double* Rs, 
     for (int64_t i = 0; i < n; ++i) AT(Rs, ldr, i, j) = 0.0;
   for (int64_t k = 0; k < n; ++k) {
     double* wk = &AT(W, ldw, 0, k);
-    double nu2 = cr64(wk, wk, k, s);
+    double nu2 = cr16(wk, wk, k, s);
     if (nu2 == 0.0 || !isfinite(nu2)) {
       *bad_k = (int32_t)k;
       free(v);
@@ -128,7 +130,7 @@ int orc_householder_r(int64_t s, int64_t n, double* W, int64_t ldw, double* Rs, 
     /* Apply H_k = I - tau v v^T to the remaining columns. */
     for (int64_t j = k + 1; j < n; ++j) {
       double* wj = &AT(W, ldw, 0, j);
-      double t = tau * cr64(v, wj, k, s);
+      double t = tau * cr16(v, wj, k, s);
       for (int64_t r = k; r < s; ++r) wj[r] = fma(-t, v[r], wj[r]);
       AT(Rs, ldr, k, j) = wj[k];
     }

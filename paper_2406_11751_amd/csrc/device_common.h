@@ -24,12 +24,18 @@ __device__ __forceinline__ int64_t sample_index(uint64_t seed, uint64_t r, uint6
   return (int64_t)__umul64hi(splitmix64_at(seed, r), m);
 }
 
-// Fixed-order 64-lane sum: lane l holds partial p_l; for h = 32,16,...,1 the
-// partials are combined as p_l + p_{l+h}.  Every lane returns p_0.
-__device__ __forceinline__ double lane_tree_sum(double p) {
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) p = p + __shfl_down(p, h, kWave);
-  return __shfl(p, 0, kWave);
+// DPP move of a double (both halves with the same control; all lanes active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
 }
 
 // Keeps the compiler from moving LDS accesses of this wave across this point;
@@ -68,9 +74,13 @@ struct Tri {
 // that order.  Padding columns j >= n never feed a column below n.
 // The triangle is consumed in groups of G values; the loads of group g+1 are
 // issued before the arithmetic of group g and a scheduling barrier closes each
-// group, so at most 2G triangle values are live in registers.
-template <int NMAX, int G>
-__device__ __forceinline__ void trsm_row(double (&t)[NMAX], const double* tri) {
+// group, so at most 2G triangle values are live in registers.  With SYNC > 0
+// the waves of the workgroup meet at a barrier every SYNC groups, so that they
+// sweep the triangle together and its values are fetched into the scalar cache
+// once per workgroup rather than once per wave (the caller must give every wave
+// of the workgroup the same number of calls).
+template <int NMAX, int G, int SYNC, typename P>
+__device__ __forceinline__ void trsm_row(double (&t)[NMAX], P tri) {
   constexpr Tri<NMAX> map{};
   constexpr int S = Tri<NMAX>::size;
   constexpr int NG = (S + G - 1) / G;
@@ -96,15 +106,12 @@ __device__ __forceinline__ void trsm_row(double (&t)[NMAX], const double* tri) {
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (SYNC > 0) {
+      if ((g + 1) % SYNC == 0) __builtin_amdgcn_s_barrier();
+    }
 #pragma unroll
     for (int i = 0; i < G; ++i) cur[i] = nxt[i];
   }
-}
-
-// Copies a packed triangle into LDS (whole workgroup; caller synchronizes).
-template <int NMAX>
-__device__ __forceinline__ void stage_tri(double* dst, const double* src) {
-  for (int e = threadIdx.x; e < Tri<NMAX>::size; e += blockDim.x) dst[e] = src[e];
 }
 
 // Makes every value of t opaque at this point: the computation producing t
@@ -113,6 +120,20 @@ template <int N>
 __device__ __forceinline__ void pin_values(double (&t)[N]) {
 #pragma unroll
   for (int j = 0; j < N; ++j) asm volatile("" : "+v"(t[j]));
+}
+
+// Constant-address-space view of a device pointer.  Loads through it are
+// eligible for the scalar memory path (s_load into SGPRs), which is how the
+// row solves receive their wave-uniform triangle values: no vector-register or
+// LDS bandwidth is spent on broadcasting them.  Only for memory that no kernel
+// writes while the reading kernel runs.
+typedef const __attribute__((address_space(4))) double* const_dptr;
+__device__ __forceinline__ const_dptr as_const(const double* p) { return (const_dptr)p; }
+
+__device__ __forceinline__ const_dptr opaque(const_dptr p) {
+  int off = 0;
+  asm volatile("" : "+s"(off));
+  return p + off;
 }
 
 // Returns p unchanged, but opaque to the optimizer: loads through the result

@@ -6,9 +6,7 @@
 // (one 512-byte coalesced load).  The row then lives in NMAX registers.
 //
 // pass A: A1 row = A row * R_s^{-1} (trsm_row), then the wave adds the panel's
-//         contribution A1_p^T A1_p to its Gram accumulator.  For NMAX <= 16
-//         each lane keeps the NMAX(NMAX+1)/2 products of its own rows and the
-//         lanes are summed once at the end; for larger NMAX the panel is
+//         contribution A1_p^T A1_p to its Gram accumulator: the panel is
 //         transposed through LDS and contracted over rows with
 //         v_mfma_f64_16x16x4f64 on the upper 16x16 block tiles.  At the end the
 //         four waves of a workgroup are summed in fixed order into one partial
@@ -16,7 +14,10 @@
 // pass B: recomputes the same A1 row with the same trsm_row code (so the bits
 //         equal those whose Gram was formed), solves with R2 and writes Q.
 //
-// The packed triangles (R_s, R2) are staged in LDS once per workgroup.
+// The packed triangles (R_s, R2) are read through the scalar memory path (see
+// trsm_row).  A workgroup's waves take panel groups in lock step (every wave
+// runs the same number of iterations; rows past m are masked), so the barriers
+// inside trsm_row are reached by all of them.
 #pragma once
 
 #include "device_common.h"
@@ -26,6 +27,7 @@ namespace rpq {
 constexpr int kPassThreads = 256;
 constexpr int kPassWaves = kPassThreads / kWave;
 constexpr int kTriGroup = 16;  // triangle values per pipelined group in trsm_row
+constexpr int kTriSync = 8;    // groups between workgroup barriers in trsm_row
 
 template <int NMAX>
 struct GramShape {
@@ -72,92 +74,33 @@ __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[N
   }
 }
 
-// pass A, per-lane Gram accumulators (NMAX <= 16).
-template <int NMAX>
-__global__ __launch_bounds__(kPassThreads) void k_passA_valu(PassAArgs a) {
-  static_assert(NMAX <= 16, "per-lane Gram only for small n");
-  constexpr int E = GramShape<NMAX>::E;  // one 16x16 tile
-  constexpr int NG = NMAX * (NMAX + 1) / 2;
-  __shared__ double red[kPassWaves * E];
-  __shared__ double tri[Tri<NMAX>::size];
-  if (a.info[0] != 0) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  stage_tri<NMAX>(tri, a.tri_s);
-  __syncthreads();
-  const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t nw = (int64_t)gridDim.x * kPassWaves;
-  double g[NG];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) g[q] = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * kPassWaves + wave; p < panels; p += nw) {
-    const int64_t r = p * kWave + lane;
-    const bool valid = r < a.m;
-    double t[NMAX];
-    load_row<NMAX>(t, a.A + r, a.lda, a.n, valid);
-    pin_values(t);
-    trsm_row<NMAX, kTriGroup>(t, opaque(tri));
-    pin_values(t);
-    if (!valid) {
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
-    }
-    store_a1<NMAX>(a, t, r, valid);
-    int q = 0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-#pragma unroll
-      for (int j = i; j < NMAX; ++j) {
-        g[q] = __builtin_fma(t[i], t[j], g[q]);
-        ++q;
-      }
-  }
-  // Sum the 64 lanes (fixed tree); lane 0 holds the wave's Gram.
-  int q = 0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double v = 0.0;
-      if (i < NMAX && j < NMAX && i <= j) {
-        v = lane_tree_sum(g[q]);
-        ++q;
-      }
-      if (lane == 0) red[wave * E + i * 16 + j] = v;
-    }
-  __syncthreads();
-  sum_waves_to_partial<E>(red, a.partials);
-}
-
-// pass A, Gram on MFMA (NMAX a multiple of 16, <= 64).
+// pass A (NMAX a multiple of 16, <= 64).
 // LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 doubles.
 template <int NMAX>
-__global__ __launch_bounds__(kPassThreads) void k_passA_mfma(PassAArgs a) {
+__global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
   static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA Gram tiles");
   constexpr int NB = GramShape<NMAX>::NB, NT = GramShape<NMAX>::NT, E = GramShape<NMAX>::E;
   constexpr int LDX = NMAX + 1;
   constexpr int XS = 32 * LDX;  // doubles per wave
   constexpr int LDS_D = (kPassWaves * XS > kPassWaves * E) ? kPassWaves * XS : kPassWaves * E;
   __shared__ double lds[LDS_D];
-  __shared__ double tri[Tri<NMAX>::size];
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  stage_tri<NMAX>(tri, a.tri_s);
-  __syncthreads();
   double* xs = lds + wave * XS;
   const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t nw = (int64_t)gridDim.x * kPassWaves;
   d4 acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   const int half_row = lane & 31;
   const int rq = lane >> 4, cq = lane & 15;  // MFMA operand position
-  for (int64_t p = (int64_t)blockIdx.x * kPassWaves + wave; p < panels; p += nw) {
-    const int64_t r = p * kWave + lane;
+  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+  for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
+    const int64_t r = (pg * kPassWaves + wave) * kWave + lane;
     const bool valid = r < a.m;
     double t[NMAX];
     load_row<NMAX>(t, a.A + r, a.lda, a.n, valid);
     pin_values(t);
-    trsm_row<NMAX, kTriGroup>(t, opaque(tri));
+    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
     pin_values(t);
     if (!valid) {
 #pragma unroll
@@ -215,23 +158,18 @@ struct PassBArgs {
 
 template <int NMAX>
 __global__ __launch_bounds__(kPassThreads) void k_passB(PassBArgs a) {
-  __shared__ double tri1[Tri<NMAX>::size];
-  __shared__ double tri2[Tri<NMAX>::size];
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  stage_tri<NMAX>(tri1, a.tri_s);
-  stage_tri<NMAX>(tri2, a.tri_2);
-  __syncthreads();
   const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t nw = (int64_t)gridDim.x * kPassWaves;
-  for (int64_t p = (int64_t)blockIdx.x * kPassWaves + wave; p < panels; p += nw) {
-    const int64_t r = p * kWave + lane;
+  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+  for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
+    const int64_t r = (pg * kPassWaves + wave) * kWave + lane;
     const bool valid = r < a.m;
     double t[NMAX];
     load_row<NMAX>(t, a.A + r, a.lda, a.n, valid);
     pin_values(t);
-    trsm_row<NMAX, kTriGroup>(t, opaque(tri1));
-    trsm_row<NMAX, kTriGroup>(t, opaque(tri2));
+    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
+    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_2)));
     pin_values(t);
     if (valid) {
       double* qrow = a.Q + r;

@@ -22,21 +22,21 @@ using namespace rpq;
 constexpr int kMaxN = 64;
 constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles in LDS
 constexpr int kPassAMaxBlocks = 512;
+static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
 constexpr int kPassBMaxBlocks = 2048;
 
 struct Plan {
   int nmax = 0, NB = 0, E = 0;
   int64_t panels = 0;
   int PA = 0, PB = 0, G2 = 0;
-  int cpw = 0, rpl = 0;  // register sketch; rpl == 0 means the generic kernel
-  size_t off_tri = 0, off_tri2 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_W = 0;
+  int rpt = 0;  // sample rows per lane in the register sketch QR; 0 = generic kernel
+  size_t off_tri = 0, off_tri2 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0;
   size_t total = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int pick_nmax(int64_t n) {
-  if (n <= 8) return 8;
   if (n <= 16) return 16;
   if (n <= 32) return 32;
   if (n <= 48) return 48;
@@ -52,12 +52,10 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
   const int64_t blocks = (p->panels + kPassWaves - 1) / kPassWaves;
   p->PA = (int)(blocks < kPassAMaxBlocks ? blocks : kPassAMaxBlocks);
   p->PB = (int)(blocks < kPassBMaxBlocks ? blocks : kPassBMaxBlocks);
-  p->G2 = (p->PA + kReduceChunk - 1) / kReduceChunk;
-  p->cpw = (int)((n + kSketchWaves - 1) / kSketchWaves);
-  if (p->cpw == 3) p->cpw = 4;
-  const int64_t rows = (s + kWave - 1) / kWave;
-  p->rpl = rows <= 1 ? 1 : rows <= 2 ? 2 : rows <= 4 ? 4 : rows <= 8 ? 8 : 0;
-  if (p->rpl == 0 && s > kMaxSketchRows) return false;
+  p->G2 = (p->PA + kReduceChunk - 1) / kReduceChunk;  // <= kMaxPartial2 since PA <= 512
+  const int64_t rows = (s + 15) / 16;
+  p->rpt = rows <= 4 ? 4 : rows <= 8 ? 8 : rows <= 12 ? 12 : rows <= 16 ? 16 : rows <= 24 ? 24 : 0;
+  if (p->rpt == 0 && s > kMaxSketchRows) return false;
   const size_t tri = (size_t)p->nmax * (p->nmax + 1) / 2 * sizeof(double);
   size_t off = 0;
   p->off_tri = off;
@@ -70,8 +68,8 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
   off = align256(off + (size_t)p->PA * p->E * sizeof(double));
   p->off_part2 = off;
   off = align256(off + (size_t)p->G2 * p->E * sizeof(double));
-  p->off_W = off;
-  if (p->rpl == 0) off = align256(off + (size_t)s * n * sizeof(double));
+  p->off_As = off;
+  off = align256(off + (size_t)s * n * sizeof(double));
   p->total = off;
   return true;
 }
@@ -85,23 +83,23 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
   return ((size_t)ld * (size_t)(cols - 1) + (size_t)rows) * sizeof(double);
 }
 
-template <int CPW>
-void launch_sketch_reg(int rpl, const SketchArgs& a, hipStream_t st) {
-  switch (rpl) {
-    case 1: hipLaunchKernelGGL((k_sketch_reg<CPW, 1>), dim3(1), dim3(kSketchThreads), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_sketch_reg<CPW, 2>), dim3(1), dim3(kSketchThreads), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_sketch_reg<CPW, 4>), dim3(1), dim3(kSketchThreads), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_sketch_reg<CPW, 8>), dim3(1), dim3(kSketchThreads), 0, st, a); break;
+void launch_sketch(const Plan& p, const SketchArgs& a, hipStream_t st) {
+  const dim3 blk(kSketchThreads);
+  switch (p.rpt) {
+    case 4: hipLaunchKernelGGL((k_sketch_qr<4>), dim3(1), blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_sketch_qr<8>), dim3(1), blk, 0, st, a); break;
+    case 12: hipLaunchKernelGGL((k_sketch_qr<12>), dim3(1), blk, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_sketch_qr<16>), dim3(1), blk, 0, st, a); break;
+    case 24: hipLaunchKernelGGL((k_sketch_qr<24>), dim3(1), blk, 0, st, a); break;
+    default:
+      hipLaunchKernelGGL(k_sketch_qr_generic, dim3(1), blk, 2 * (size_t)a.s * sizeof(double), st, a);
+      break;
   }
 }
 
 template <int NMAX>
 void launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
-  if constexpr (NMAX <= 16) {
-    hipLaunchKernelGGL((k_passA_valu<NMAX>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_passA_mfma<NMAX>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
-  }
+  hipLaunchKernelGGL((k_passA_mfma<NMAX>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
 }
 
 template <int NMAX>
@@ -173,19 +171,14 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   sa.Rs = Rs_ws;
   sa.nmax = p.nmax;
   sa.info = inf;
-  sa.W = (double*)(base + p.off_W);
+  sa.As = (double*)(base + p.off_As);
   sa.idx_out = idx;
   sa.As_out = As;
   sa.Rs_out = Rs;
-  if (p.rpl > 0) {
-    switch (p.cpw) {
-      case 1: launch_sketch_reg<1>(p.rpl, sa, st); break;
-      case 2: launch_sketch_reg<2>(p.rpl, sa, st); break;
-      default: launch_sketch_reg<4>(p.rpl, sa, st); break;
-    }
-  } else {
-    hipLaunchKernelGGL(k_sketch_global, dim3(1), dim3(kSketchThreads), 2 * (size_t)s * sizeof(double), st, sa);
-  }
+  const int64_t gather_blocks = ((int64_t)s * n + kGatherThreads - 1) / kGatherThreads;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
+  if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  launch_sketch(p, sa, st);
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
@@ -200,7 +193,6 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pa.info = inf;
   pa.A1 = A1;
   switch (p.nmax) {
-    case 8: launch_passes_A<8>(p, pa, st); break;
     case 16: launch_passes_A<16>(p, pa, st); break;
     case 32: launch_passes_A<32>(p, pa, st); break;
     case 48: launch_passes_A<48>(p, pa, st); break;
@@ -245,7 +237,6 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pb.ldq = ldq;
   pb.info = inf;
   switch (p.nmax) {
-    case 8: launch_pass_B<8>(p, pb, st); break;
     case 16: launch_pass_B<16>(p, pb, st); break;
     case 32: launch_pass_B<32>(p, pb, st); break;
     case 48: launch_pass_B<48>(p, pb, st); break;

@@ -1,26 +1,45 @@
 // Sampling, scaled gather and Householder QR of the sample (Algorithm
-// rpCholesky-QR, lines 2-3), in one workgroup of 16 waves.
+// rpCholesky-QR, lines 2-3).
 //
-// Ownership: wave w owns the sample columns j = w, w+16, w+32, ...; lane l owns
-// the sample rows r = l, l+64, l+128, ...  Every element of the working matrix
-// is touched by exactly one thread, so only the Householder vector, tau and the
-// R factor are shared (through LDS).
+// k_gather (many workgroups): idx_r = SplitMix64 index r, A_s = sqrt(m/s) A(idx, :)
+// into the workspace (s x n, ld s).  Spreading the s*n random reads over the
+// whole chip matters: one workgroup cannot keep enough of them in flight.
 //
-// Dot products over rows r >= k use the fixed order of lane_tree_sum: lane l
-// accumulates its rows in ascending order with fma, then the 64 partials are
-// combined pairwise.  With beta = -sign(alpha) * nu, d = 1/(alpha - beta),
-// v = (1, y_1 d, ...), tau = (beta - alpha)/beta and the update
-// w_r = fma(-tau*(v.w), v_r, w_r), this fixes every rounding of R_s.
+// k_sketch_qr (one workgroup of 16 waves): Householder QR of A_s, R only.
+// Column j lives in the 16-lane row q = j / 16 of wave j mod 16; lane l16 of
+// that row holds sample rows r = l16 + 16t.  Each element is touched by one
+// thread only; the Householder vector, tau and R go through LDS.
+//
+// Every dot product over rows r >= k uses one fixed order: lane l16 accumulates
+// its rows in ascending r with fma, then the 16 partials are combined by an
+// XOR butterfly (h = 1, 2, 4, 8), whose result equals the pairwise tree
+// p_i += p_{i+h} and is identical in all 16 lanes.  With beta = -sign(alpha) nu,
+// d = 1/(alpha - beta), v = (1, y_1 d, ...), tau = (beta - alpha)/beta and the
+// update w_r = fma(-tau (v.w), v_r, w_r), this fixes every rounding of R_s.
 #pragma once
+
+#include <type_traits>
+#include <utility>
 
 #include "device_common.h"
 
 namespace rpq {
 
+// Calls f(integral_constant<int, i>) for i = 0..N-1 (compile-time loop).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 constexpr int kSketchWaves = 16;
 constexpr int kSketchThreads = kSketchWaves * kWave;
-constexpr int kSketchMaxN = 64;  // R_s is staged in LDS as 64 x 65
+constexpr int kSketchMaxN = 64;  // 16 waves x 4 rows of 16 lanes; R_s staged in LDS as 64 x 65
 constexpr int kSketchLdr = kSketchMaxN + 1;
+constexpr int kGatherThreads = 256;
 
 struct SketchArgs {
   int64_t m;
@@ -29,15 +48,38 @@ struct SketchArgs {
   double scale;  // sqrt(m/s), correctly rounded on the host
   const double* A;
   int64_t lda;
+  double* As;     // workspace: scaled sample, s x n, ld s (the generic QR works on it in place)
   double* tri;    // out: packed R_s for the row solves (see Tri), nmax rows
   double* Rs;     // out: R_s, n x n column-major (ld n)
   int32_t nmax;
   int32_t* info;  // {code, index}
-  double* W;      // global working copy of A_s (s x n, ld s), used by the generic kernel only
   int64_t* idx_out;  // optional
   double* As_out;    // optional, s x n, ld s
   double* Rs_out;    // optional, n x n, ld n
 };
+
+// Line 2: one thread per sample entry.
+__global__ __launch_bounds__(kGatherThreads) void k_gather(SketchArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * kGatherThreads + threadIdx.x;
+  const int64_t total = (int64_t)a.s * a.n;
+  if (e >= total) return;
+  const int r = (int)(e % a.s), j = (int)(e / a.s);
+  const int64_t ir = sample_index(a.seed, (uint64_t)r, (uint64_t)a.m);
+  const double v = a.scale * a.A[ir + (int64_t)j * a.lda];
+  a.As[e] = v;
+  if (a.As_out) a.As_out[e] = v;
+  if (a.idx_out && j == 0) a.idx_out[r] = ir;
+}
+
+// XOR butterfly over the 16 lanes of a row (all lanes active):
+// h = 1, 2 by quad permutation, h = 4 by half-row mirror, h = 8 by row mirror.
+__device__ __forceinline__ double row16_sum(double p) {
+  p = p + dpp_d<0xB1>(p);   // quad_perm [1,0,3,2]
+  p = p + dpp_d<0x4E>(p);   // quad_perm [2,3,0,1]
+  p = p + dpp_d<0x141>(p);  // row_half_mirror
+  p = p + dpp_d<0x140>(p);  // row_mirror
+  return p;
+}
 
 // Sign-normalize R_s (negate rows with a negative diagonal; exact) and write
 // the packed triangle for the row solves, the column-major copy and the
@@ -73,211 +115,192 @@ __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double*
   }
 }
 
-// Register-resident variant: each lane keeps CPW x RPL entries of A_s.
-// Requires n <= 16*CPW <= 64 and s <= 64*RPL.
-template <int CPW, int RPL>
-__global__ __launch_bounds__(kSketchThreads) void k_sketch_reg(SketchArgs a) {
-  __shared__ double vbuf[2][RPL * kWave];
+__device__ __forceinline__ void sketch_status(const SketchArgs& a, int bad_k) {
+  if (threadIdx.x == 0) {
+    a.info[0] = bad_k >= 0 ? 1 : 0;
+    a.info[1] = bad_k;
+  }
+}
+
+// Line 3 with the sample in registers: RPT rows per lane (s <= 16 RPT), n <= 64.
+// One barrier per Householder step: during step k every wave applies reflector
+// k to its four columns, and the wave owning column k+1 then forms reflector
+// k+1 from the freshly updated column into the other LDS buffer.
+template <int RPT>
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
+  __shared__ double vbuf[2][16 * RPT];
   __shared__ double tau_s[2];
   __shared__ double Rl[kSketchMaxN * kSketchLdr];
-  __shared__ int bad_k;
+  // bad[k & 1] = k when reflector k has a zero or non-finite norm.  Written by
+  // the wave forming reflector k during step k-1, read by all after the barrier
+  // that ends step k-1: never read and written in the same step.
+  __shared__ int bad[2];
 
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int j = wave + 16 * q;  // my column
   const int n = a.n, s = a.s;
 
   for (int e = threadIdx.x; e < kSketchMaxN * kSketchLdr; e += kSketchThreads) Rl[e] = 0.0;
-  if (threadIdx.x == 0) bad_k = -1;
-
-  // Line 2: indices of my rows, then the scaled gather.
-  int64_t rowidx[RPL];
+  if (threadIdx.x < 2) bad[threadIdx.x] = -1;
+  double W[RPT];
 #pragma unroll
-  for (int t = 0; t < RPL; ++t) {
-    const int r = lane + kWave * t;
-    rowidx[t] = (r < s) ? sample_index(a.seed, (uint64_t)r, (uint64_t)a.m) : 0;
-    if (a.idx_out && wave == 0 && r < s) a.idx_out[r] = rowidx[t];
-  }
-  double W[CPW][RPL];
-#pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    const int j = wave + kSketchWaves * c;
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int r = lane + kWave * t;
-      double v = 0.0;
-      if (j < n && r < s) {
-        v = a.scale * a.A[rowidx[t] + (int64_t)j * a.lda];
-        if (a.As_out) a.As_out[r + (int64_t)j * s] = v;
-      }
-      W[c][t] = v;
-    }
+  for (int t = 0; t < RPT; ++t) {
+    const int r = l16 + 16 * t;
+    W[t] = (j < n && r < s) ? a.As[r + (int64_t)j * s] : 0.0;
   }
   __syncthreads();
 
-  // Line 3: Householder QR, R only.
-  for (int k = 0; k < n; ++k) {
-    const int owner = k & (kSketchWaves - 1), kc = k >> 4, kt = k >> 6, kl = k & (kWave - 1);
+  // Reflector k from my column (this wave owns column k; its row KB = k / 16
+  // holds it, row k of it sits in lane k, slot KB).
+  auto reflector = [&](auto kb, int k) __attribute__((always_inline)) {
+    constexpr int KB = decltype(kb)::value;
     const int buf = k & 1;
-    if (wave == owner) {
-      double col[RPL];
+    double p = 0.0;
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        double v = W[0][t];
+    for (int t = 0; t < RPT; ++t) {
+      const int r = l16 + 16 * t;
+      const double x = (r >= k) ? W[t] : 0.0;
+      p = __builtin_fma(x, x, p);
+    }
+    const double nu2 = readlane_d(row16_sum(p), k);
+    const double alpha = readlane_d(W[KB], k);
+    if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
+      if (lane == 0) bad[buf] = k;
+      return;
+    }
+    const double nu = __builtin_sqrt(nu2);
+    const double beta = (alpha >= 0.0) ? -nu : nu;
+    const double d = 1.0 / (alpha - beta);
+    const double tau = (beta - alpha) / beta;
+    if (q == KB) {
 #pragma unroll
-        for (int c = 1; c < CPW; ++c)
-          if (c == kc) v = W[c][t];
-        col[t] = v;
-      }
-      double p = 0.0;
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int r = lane + kWave * t;
-        if (r >= k && r < s) p = __builtin_fma(col[t], col[t], p);
-      }
-      const double nu2 = lane_tree_sum(p);
-      double ak = col[0];
-#pragma unroll
-      for (int t = 1; t < RPL; ++t)
-        if (t == kt) ak = col[t];
-      const double alpha = __shfl(ak, kl, kWave);
-      if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
-        if (lane == 0) bad_k = k;
-      } else {
-        const double nu = __builtin_sqrt(nu2);
-        const double beta = (alpha >= 0.0) ? -nu : nu;
-        const double d = 1.0 / (alpha - beta);
-        const double tau = (beta - alpha) / beta;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + kWave * t;
-          if (r >= k && r < s) vbuf[buf][r] = (r == k) ? 1.0 : col[t] * d;
-        }
-        if (lane == 0) {
-          tau_s[buf] = tau;
-          Rl[k * kSketchLdr + k] = beta;
-        }
+      for (int t = 0; t < RPT; ++t) {
+        const int r = l16 + 16 * t;
+        if (r >= k && r < s) vbuf[buf][r] = (r == k) ? 1.0 : W[t] * d;
       }
     }
-    __syncthreads();
-    if (bad_k >= 0) break;
+    if (lane == 0) {
+      tau_s[buf] = tau;
+      Rl[k * kSketchLdr + k] = beta;
+    }
+  };
+
+  // Reflector k applied to my column.  Rows r < k enter the dot product and
+  // the update with a zero Householder entry: they add exact zeros and are
+  // left unchanged (those rows of the column are already final in R).
+  auto apply = [&](auto kb, int k) __attribute__((always_inline)) {
+    constexpr int KB = decltype(kb)::value;
+    const int buf = k & 1;
     const double tau = tau_s[buf];
+    double vk[RPT];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      const int j = wave + kSketchWaves * c;
-      if (j > k && j < n) {
-        double p = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + kWave * t;
-          if (r >= k && r < s) p = __builtin_fma(vbuf[buf][r], W[c][t], p);
-        }
-        const double tt = tau * lane_tree_sum(p);
-        double rk = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + kWave * t;
-          if (r >= k && r < s) W[c][t] = __builtin_fma(-tt, vbuf[buf][r], W[c][t]);
-          if (t == kt) rk = W[c][t];
-        }
-        if (lane == kl) Rl[k * kSketchLdr + j] = rk;
-      }
+    for (int t = 0; t < RPT; ++t) {
+      const int r = l16 + 16 * t;
+      vk[t] = (r >= k && r < s) ? vbuf[buf][r] : 0.0;
     }
-  }
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) p = __builtin_fma(vk[t], W[t], p);
+    const double tt = tau * row16_sum(p);
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vk[t], W[t]);
+    if (l16 == (k & 15) && j > k && j < n) Rl[k * kSketchLdr + j] = W[KB];
+  };
+
+  if (wave == 0) reflector(std::integral_constant<int, 0>{}, 0);
   __syncthreads();
-  if (bad_k >= 0) {
-    if (threadIdx.x == 0) {
-      a.info[0] = 1;
-      a.info[1] = bad_k;
+  static_for<4>([&](auto kbI) __attribute__((always_inline)) {
+    constexpr int KB = decltype(kbI)::value;
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * KB + kk;
+      if (k >= n || bad[k & 1] >= 0) break;
+      apply(std::integral_constant<int, KB>{}, k);
+      if (k + 1 < n && wave == ((k + 1) & 15)) {
+        if (kk < 15)
+          reflector(std::integral_constant<int, KB>{}, k + 1);
+        else if constexpr (KB < 3)
+          reflector(std::integral_constant<int, KB + 1>{}, k + 1);
+      }
+      __syncthreads();
     }
-    return;
-  }
-  if (threadIdx.x == 0) {
-    a.info[0] = 0;
-    a.info[1] = -1;
-  }
+  });
+  const int bad_k = bad[0] >= 0 ? bad[0] : bad[1];
+  sketch_status(a, bad_k);
+  if (bad_k >= 0) return;
   sketch_finish(a, Rl);
 }
 
-// Generic variant: the working copy of A_s lives in global memory (a.W, s x n,
-// ld s); the Householder vector in dynamic LDS (2*s doubles).  Same ownership
-// and the same operation order as k_sketch_reg.  Requires n <= 64.
-__global__ __launch_bounds__(kSketchThreads) void k_sketch_global(SketchArgs a) {
+// Line 3 for large s: the same layout and operation order, with the sample
+// kept in global memory (a.As, worked on in place) and the Householder vector
+// in dynamic LDS (2 s doubles).  n <= 64.
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs a) {
   extern __shared__ double vdyn[];  // [2][s]
   __shared__ double tau_s[2];
   __shared__ double Rl[kSketchMaxN * kSketchLdr];
-  __shared__ int bad_k;
+  __shared__ int bad[2];  // as in k_sketch_qr
 
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int j = wave + 16 * q;
   const int n = a.n, s = a.s;
-  double* W = a.W;
+  const bool mine = j < n;
+  double* W = a.As + (int64_t)(mine ? j : 0) * s;  // my column (padding columns never write)
 
   for (int e = threadIdx.x; e < kSketchMaxN * kSketchLdr; e += kSketchThreads) Rl[e] = 0.0;
-  if (threadIdx.x == 0) bad_k = -1;
-  for (int r = lane; r < s; r += kWave) {
-    const int64_t ir = sample_index(a.seed, (uint64_t)r, (uint64_t)a.m);
-    if (a.idx_out && wave == 0) a.idx_out[r] = ir;
-    for (int j = wave; j < n; j += kSketchWaves) {
-      const double v = a.scale * a.A[ir + (int64_t)j * a.lda];
-      W[r + (int64_t)j * s] = v;
-      if (a.As_out) a.As_out[r + (int64_t)j * s] = v;
-    }
-  }
+  if (threadIdx.x < 2) bad[threadIdx.x] = -1;
   __syncthreads();
 
-  for (int k = 0; k < n; ++k) {
-    const int owner = k & (kSketchWaves - 1);
-    const int buf = k & 1;
-    double* vb = vdyn + (size_t)buf * s;
-    if (wave == owner) {
-      const double* col = W + (int64_t)k * s;
+  for (int k = -1; k < n; ++k) {
+    if (k >= 0 && bad[k & 1] >= 0) break;
+    if (k >= 0) {
+      const int buf = k & 1;
+      const double* vb = vdyn + (size_t)buf * s;
+      const double tau = tau_s[buf];
       double p = 0.0;
-      for (int r = lane; r < s; r += kWave)
-        if (r >= k) p = __builtin_fma(col[r], col[r], p);
-      const double nu2 = lane_tree_sum(p);
-      const double alpha = col[k];
+      for (int r = l16; r < s; r += 16) {
+        const double v = (r >= k) ? vb[r] : 0.0;
+        p = __builtin_fma(v, mine ? W[r] : 0.0, p);
+      }
+      const double tt = tau * row16_sum(p);
+      if (mine) {
+        for (int r = l16; r < s; r += 16)
+          if (r >= k) W[r] = __builtin_fma(-tt, vb[r], W[r]);
+        if (l16 == (k & 15) && j > k) Rl[k * kSketchLdr + j] = W[k];
+      }
+    }
+    const int k1 = k + 1;
+    if (k1 < n && wave == (k1 & 15)) {
+      // Column k1 lives in row k1 / 16 of this wave; its row k1 is held by lane k1.
+      double p = 0.0;
+      for (int r = l16; r < s; r += 16) {
+        const double x = (r >= k1 && mine) ? W[r] : 0.0;
+        p = __builtin_fma(x, x, p);
+      }
+      const double nu2 = readlane_d(row16_sum(p), k1);
+      const double alpha = readlane_d(lane == k1 ? W[k1] : 0.0, k1);
       if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
-        if (lane == 0) bad_k = k;
+        if (lane == 0) bad[k1 & 1] = k1;
       } else {
         const double nu = __builtin_sqrt(nu2);
         const double beta = (alpha >= 0.0) ? -nu : nu;
         const double d = 1.0 / (alpha - beta);
         const double tau = (beta - alpha) / beta;
-        for (int r = lane; r < s; r += kWave)
-          if (r >= k) vb[r] = (r == k) ? 1.0 : col[r] * d;
+        double* vb = vdyn + (size_t)(k1 & 1) * s;
+        if (q == (k1 >> 4))
+          for (int r = l16; r < s; r += 16)
+            if (r >= k1) vb[r] = (r == k1) ? 1.0 : W[r] * d;
         if (lane == 0) {
-          tau_s[buf] = tau;
-          Rl[k * kSketchLdr + k] = beta;
+          tau_s[k1 & 1] = tau;
+          Rl[k1 * kSketchLdr + k1] = beta;
         }
       }
     }
     __syncthreads();
-    if (bad_k >= 0) break;
-    const double tau = tau_s[buf];
-    for (int j = wave; j < n; j += kSketchWaves) {
-      if (j <= k) continue;
-      double* wj = W + (int64_t)j * s;
-      double p = 0.0;
-      for (int r = lane; r < s; r += kWave)
-        if (r >= k) p = __builtin_fma(vb[r], wj[r], p);
-      const double tt = tau * lane_tree_sum(p);
-      for (int r = lane; r < s; r += kWave)
-        if (r >= k) wj[r] = __builtin_fma(-tt, vb[r], wj[r]);
-      if (lane == (k & (kWave - 1))) Rl[k * kSketchLdr + j] = wj[k];
-    }
   }
-  __syncthreads();
-  if (bad_k >= 0) {
-    if (threadIdx.x == 0) {
-      a.info[0] = 1;
-      a.info[1] = bad_k;
-    }
-    return;
-  }
-  if (threadIdx.x == 0) {
-    a.info[0] = 0;
-    a.info[1] = -1;
-  }
+  const int bad_k = bad[0] >= 0 ? bad[0] : bad[1];
+  sketch_status(a, bad_k);
+  if (bad_k >= 0) return;
   sketch_finish(a, Rl);
 }
 

@@ -9,7 +9,8 @@ namespace rpq {
 
 constexpr int kReduceThreads = 256;
 constexpr int kReduceChunk = 32;  // partials summed per thread in the first level
-constexpr int kCholThreads = 1024;
+constexpr int kMaxPartial2 = 16;  // second-level partials (first-level chunks) at most
+constexpr int kCholThreads = 256;
 constexpr int kCholMaxN = 64;
 constexpr int kCholLdg = kCholMaxN + 1;
 
@@ -23,9 +24,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double
   const int e = blockIdx.x * kReduceThreads + threadIdx.x;
   if (e >= E) return;
   const int p0 = blockIdx.y * kReduceChunk;
-  const int p1 = min(P, p0 + kReduceChunk);
-  double acc = 0.0;
-  for (int p = p0; p < p1; ++p) acc = acc + partials[(int64_t)p * E + e];
+  const int cnt = min(P - p0, kReduceChunk);
+  // All loads first (independent), then the sum in ascending p.
+  double v[kReduceChunk];
+#pragma unroll
+  for (int q = 0; q < kReduceChunk; ++q) v[q] = (q < cnt) ? partials[(int64_t)(p0 + q) * E + e] : 0.0;
+  double acc = v[0];
+#pragma unroll
+  for (int q = 1; q < kReduceChunk; ++q)
+    if (q < cnt) acc = acc + v[q];
   partial2[(int64_t)blockIdx.y * E + e] = acc;
 }
 
@@ -42,15 +49,23 @@ struct CholArgs {
   double* R2_out;       // optional n x n, ld n
 };
 
-// One workgroup.  Right-looking Cholesky on the LDS copy of G1: at step k the
-// pivot row is scaled by 1/sqrt(G(k,k)) and the trailing upper triangle gets
-// G(i,j) -= R(k,i) R(k,j).  Non-positive or non-finite pivot -> ECHOL(k).
+// One workgroup.  The second-level partials are summed by all threads; the
+// Cholesky factorization runs in wave 0 with lane j holding column j of G1 in
+// registers (right-looking: at step k the pivot row is scaled by sqrt(G(k,k))
+// and broadcast through LDS, then every lane j updates G(i,j) -= R(k,i) R(k,j)
+// for i > k).  A non-positive or non-finite pivot gives ECHOL(k).
 __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
   __shared__ double G[kCholMaxN * kCholLdg];
+  __shared__ double Rs_l[kCholMaxN * kCholLdg];  // R_s row-major
+  __shared__ double rowk[kCholMaxN];
+  __shared__ int bad_s;
   if (a.info[0] != 0) return;
   const int n = a.n, tid = threadIdx.x;
+  if (tid == 0) bad_s = -1;
 
-  // Assemble G1 from the second-level partials (ascending g).
+  // Stage R_s for the R product and assemble G1 from the second-level
+  // partials (independent loads first, then the sum in ascending g).
+  for (int e = tid; e < n * n; e += kCholThreads) Rs_l[(e % n) * kCholLdg + e / n] = a.Rs[e];
   for (int e = tid; e < a.E; e += kCholThreads) {
     const int tile = e >> 8, w = e & 255;
     int bi = 0, rem = tile;
@@ -61,8 +76,13 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     const int bj = bi + rem;
     const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
     if (i <= j && j < n) {
-      double acc = 0.0;
-      for (int g = 0; g < a.G2; ++g) acc = acc + a.partial2[(int64_t)g * a.E + e];
+      double v[kMaxPartial2];
+#pragma unroll
+      for (int g = 0; g < kMaxPartial2; ++g) v[g] = (g < a.G2) ? a.partial2[(int64_t)g * a.E + e] : 0.0;
+      double acc = v[0];
+#pragma unroll
+      for (int g = 1; g < kMaxPartial2; ++g)
+        if (g < a.G2) acc = acc + v[g];
       G[i * kCholLdg + j] = acc;
     }
   }
@@ -73,31 +93,42 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
       a.G1_out[e] = (i <= j) ? G[i * kCholLdg + j] : 0.0;
     }
   }
-  __syncthreads();
 
-  int bad = -1;
-  for (int k = 0; k < n; ++k) {
-    const double d = G[k * kCholLdg + k];
-    if (!(d > 0.0) || !__builtin_isfinite(d)) {
-      bad = k;
-      break;
+  if (tid < kWave) {
+    const int lane = tid;
+    double g[kCholMaxN];
+#pragma unroll
+    for (int i = 0; i < kCholMaxN; ++i) g[i] = (i <= lane && lane < n) ? G[i * kCholLdg + lane] : 0.0;
+    int bad = -1;
+#pragma unroll
+    for (int k = 0; k < kCholMaxN; ++k) {
+      if (k >= n || bad >= 0) break;
+      const double d = readlane_d(g[k], k);
+      if (!(d > 0.0) || !__builtin_isfinite(d)) {
+        bad = k;
+        break;
+      }
+      const double rkk = __builtin_sqrt(d);
+      g[k] = (lane == k) ? rkk : g[k] / rkk;
+      rowk[lane] = g[k];
+      wave_lds_fence();
+#pragma unroll
+      for (int i = k + 1; i < kCholMaxN; ++i) g[i] = __builtin_fma(-rowk[i], g[k], g[i]);
+      wave_lds_fence();
     }
-    const double rkk = __builtin_sqrt(d);
-    __syncthreads();  // everyone has read G(k,k)
-    for (int j = k + tid; j < n; j += kCholThreads)
-      G[k * kCholLdg + j] = (j == k) ? rkk : G[k * kCholLdg + j] / rkk;
-    __syncthreads();
-    const int w = n - k - 1;
-    for (int e = tid; e < w * w; e += kCholThreads) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      if (i <= j) G[i * kCholLdg + j] = __builtin_fma(-G[k * kCholLdg + i], G[k * kCholLdg + j], G[i * kCholLdg + j]);
+    // Write R2 back into G's upper triangle (lane j owns column j).
+    if (lane < n) {
+#pragma unroll
+      for (int i = 0; i < kCholMaxN; ++i)
+        if (i <= lane) G[i * kCholLdg + lane] = g[i];
     }
-    __syncthreads();
+    if (lane == 0) bad_s = bad;
   }
-  if (bad >= 0) {
+  __syncthreads();
+  if (bad_s >= 0) {
     if (tid == 0) {
       a.info[0] = 2;
-      a.info[1] = bad;
+      a.info[1] = bad_s;
     }
     return;
   }
@@ -126,7 +157,7 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     const int i = e % n, j = e / n;
     double acc = 0.0;
     if (i <= j)
-      for (int k = i; k <= j; ++k) acc = __builtin_fma(G[i * kCholLdg + k], a.Rs[k + (int64_t)j * n], acc);
+      for (int k = i; k <= j; ++k) acc = __builtin_fma(G[i * kCholLdg + k], Rs_l[k * kCholLdg + j], acc);
     a.R[i + (int64_t)j * a.ldr] = acc;
   }
 }

@@ -47,10 +47,11 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100, 0, 5) == 0        # n < 1
     assert rq.workspace_bytes(1000, rq.max_n() + 1, 500) == 0
     assert rq.workspace_bytes(100, 10, 30, precision=7) == 0
-    # the workspace grows with the generic sketch path (s > 512) by s*n doubles
-    small = rq.workspace_bytes(100_000, 32, 512)
-    big = rq.workspace_bytes(100_000, 32, 600)
-    assert big - small >= 600 * 32 * 8
+    # the workspace holds the s x n scaled sample and grows with s
+    for s in (96, 384, 385, 1536):
+        assert rq.workspace_bytes(100_000, 32, s) >= s * 32 * 8
+    assert rq.workspace_bytes(100_000, 32, 1536) > rq.workspace_bytes(100_000, 32, 96)
+    assert rq.workspace_bytes(100_000, 32, 1537) == 0  # beyond the largest supported sample
 
 
 def test_missing_library_fails_loudly(monkeypatch):
