@@ -5,16 +5,17 @@
 // each column j the 64 lanes load 64 consecutive doubles of column-major A
 // (one 512-byte coalesced load).  The row then lives in NMAX registers.
 //
-// pass A: A1 row = A row * R_s^{-1} (trsm_row), then the wave adds the panel's
-//         contribution A1_p^T A1_p to its Gram accumulator: the panel is
-//         transposed through LDS and contracted over rows with
-//         v_mfma_f64_16x16x4f64 on the upper 16x16 block tiles.  At the end the
-//         four waves of a workgroup are summed in fixed order into one partial
-//         Gram per workgroup (upper block tiles, 256 doubles each).
-// pass B: recomputes the same A1 row with the same trsm_row code (so the bits
-//         equal those whose Gram was formed), solves with R2 and writes Q.
+// pass A: A1 row = A row * R_s^{-1} (trsm_row), stored into the Q buffer, and
+//         the wave adds the panel's contribution A1_p^T A1_p to its Gram
+//         accumulator: the panel is transposed through LDS and contracted over
+//         rows with v_mfma_f64_16x16x4f64 on the upper 16x16 block tiles.  At
+//         the end the four waves of a workgroup are summed in fixed order into
+//         one partial Gram per workgroup (upper block tiles, 256 doubles each).
+// pass B: Q = A1 R2^{-1}, in place in the Q buffer, on MFMA (see k_passB).
+//         Reading back the stored A1 means the solve uses exactly the bits whose
+//         Gram was formed.
 //
-// The packed triangles (R_s, R2) are read through the scalar memory path (see
+// The packed triangle R_s is read through the scalar memory path (see
 // trsm_row).  A workgroup's waves take panel groups in lock step (every wave
 // runs the same number of iterations; rows past m are masked), so the barriers
 // inside trsm_row are reached by all of them.
@@ -36,11 +37,17 @@ struct GramShape {
   static constexpr int E = NT * 256;              // doubles per partial Gram
 };
 
+// Row `lane` of the panel starting at row r0: the column base pointers are
+// wave-uniform (scalar registers), the lane adds its offset.  n and lda are
+// made opaque per call so that the column guards and column offsets are
+// recomputed per panel instead of being hoisted into NMAX live scalar pairs.
 template <int NMAX>
-__device__ __forceinline__ void load_row(double (&t)[NMAX], const double* __restrict__ arow, int64_t lda,
-                                         int n, bool valid) {
+__device__ __forceinline__ void load_row(double (&t)[NMAX], const double* __restrict__ A, int64_t r0, int64_t lda,
+                                         int n, int lane, bool valid) {
+  asm volatile("" : "+s"(n), "+s"(lda));
+  const double* base = A + r0;
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j) t[j] = (valid && j < n) ? arow[(int64_t)j * lda] : 0.0;
+  for (int j = 0; j < NMAX; ++j) t[j] = (valid && j < n) ? (base + (int64_t)j * lda)[lane] : 0.0;
 }
 
 struct PassAArgs {
@@ -51,7 +58,8 @@ struct PassAArgs {
   const double* tri_s;  // packed R_s (see Tri)
   double* partials;     // [gridDim.x][E]
   const int32_t* info;
-  double* A1;           // optional m x n, ld m
+  double* W;            // A1 out (the Q buffer), m x n, ld ldw
+  int64_t ldw;
 };
 
 // Final cross-wave sum: each wave stored its tiles in LDS red[wave][E].
@@ -66,11 +74,16 @@ __device__ __forceinline__ void sum_waves_to_partial(const double* red, double* 
 }
 
 template <int NMAX>
-__device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[NMAX], int64_t r, bool valid) {
-  if (a.A1 && valid) {
+__device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[NMAX], int64_t r0, int lane,
+                                         bool valid) {
+  int n = a.n;
+  int64_t ldw = a.ldw;
+  asm volatile("" : "+s"(n), "+s"(ldw));
+  double* base = a.W + r0;
+  if (valid) {
 #pragma unroll
     for (int j = 0; j < NMAX; ++j)
-      if (j < a.n) a.A1[r + (int64_t)j * a.m] = t[j];
+      if (j < n) (base + (int64_t)j * ldw)[lane] = t[j];
   }
 }
 
@@ -95,10 +108,10 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
   const int rq = lane >> 4, cq = lane & 15;  // MFMA operand position
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
   for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
-    const int64_t r = (pg * kPassWaves + wave) * kWave + lane;
-    const bool valid = r < a.m;
+    const int64_t r0 = (pg * kPassWaves + wave) * kWave;
+    const bool valid = r0 + lane < a.m;
     double t[NMAX];
-    load_row<NMAX>(t, a.A + r, a.lda, a.n, valid);
+    load_row<NMAX>(t, a.A, r0, a.lda, a.n, lane, valid);
     pin_values(t);
     trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
     pin_values(t);
@@ -106,7 +119,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
 #pragma unroll
       for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
     }
-    store_a1<NMAX>(a, t, r, valid);
+    store_a1<NMAX>(a, t, r0, lane, valid);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       wave_lds_fence();
@@ -147,35 +160,70 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
 struct PassBArgs {
   int64_t m;
   int32_t n;
-  const double* A;
-  int64_t lda;
-  const double* tri_s;  // packed R_s
-  const double* tri_2;  // packed R2
-  double* Q;
+  const double* T2;     // R2^{-1}, NMAX x NMAX row-major, zero outside the n x n upper triangle
+  double* Q;            // holds A1 on entry, Q on exit
   int64_t ldq;
   const int32_t* info;
 };
 
+constexpr int kPassBThreads = 256;
+
+// pass B: Q = A1 R2^{-1} with the explicit inverse T2 (R2 is well conditioned:
+// kappa(R2) = kappa(A1)), one 16-row block at a time, formed transposed,
+// Q^T = T2^T A1^T, on v_mfma_f64_16x16x4f64:
+//   operand A (i, kk) = T2(4 kc + kk, 16 cb + i): lane l holds T2(4 kc + l/16, 16 cb + l%16),
+//                       the same for every block, so it stays in registers;
+//   operand B (kk, j) = A1(r0 + j, 4 kc + kk):   lane l loads A1(r0 + l%16, 4 kc + l/16),
+//                       four 128-byte column segments per load;
+//   result D (i, j) = Q(r0 + j, 16 cb + i) in lane j + 16 (i%4), register i/4,
+//                       stored as four 128-byte column segments per store.
+// All loads of a block are issued before its stores, so the update is in place.
 template <int NMAX>
-__global__ __launch_bounds__(kPassThreads) void k_passB(PassBArgs a) {
+__global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
+  static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA tiles");
+  constexpr int NB = NMAX / 16, NKC = NMAX / 4;
+  constexpr int NOPS = NKC * NB - 2 * NB * (NB - 1);  // (kc, cb) pairs with cb >= kc / 4
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-  for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
-    const int64_t r = (pg * kPassWaves + wave) * kWave + lane;
-    const bool valid = r < a.m;
-    double t[NMAX];
-    load_row<NMAX>(t, a.A + r, a.lda, a.n, valid);
-    pin_values(t);
-    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
-    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_2)));
-    pin_values(t);
-    if (valid) {
-      double* qrow = a.Q + r;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  double t2[NOPS];
+  {
+    int o = 0;
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j)
-        if (j < a.n) qrow[(int64_t)j * a.ldq] = t[j];
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int cb = kc / 4; cb < NB; ++cb) t2[o++] = a.T2[(4 * kc + g4) * NMAX + 16 * cb + i16];
+  }
+  const int64_t blocks = (a.m + 15) / 16;
+  const int64_t nw = (int64_t)gridDim.x * (kPassBThreads / kWave);
+  for (int64_t blk = (int64_t)blockIdx.x * (kPassBThreads / kWave) + wave; blk < blocks; blk += nw) {
+    const int64_t row = blk * 16 + i16;
+    const bool rvalid = row < a.m;
+    double x[NKC];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      const int col = 4 * kc + g4;
+      x[kc] = (rvalid && col < a.n) ? a.Q[row + (int64_t)col * a.ldq] : 0.0;
+    }
+    d4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    int o = 0;
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int cb = kc / 4; cb < NB; ++cb) {
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(t2[o], x[kc], acc[cb], 0, 0, 0);
+        ++o;
+      }
+    if (rvalid) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * cb + g4 + 4 * v;
+          if (col < a.n) a.Q[row + (int64_t)col * a.ldq] = acc[cb][v];
+        }
     }
   }
 }

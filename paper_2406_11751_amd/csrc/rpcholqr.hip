@@ -51,7 +51,8 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
   p->panels = (m + kWave - 1) / kWave;
   const int64_t blocks = (p->panels + kPassWaves - 1) / kPassWaves;
   p->PA = (int)(blocks < kPassAMaxBlocks ? blocks : kPassAMaxBlocks);
-  p->PB = (int)(blocks < kPassBMaxBlocks ? blocks : kPassBMaxBlocks);
+  const int64_t bblocks = ((m + 15) / 16 + kPassBThreads / kWave - 1) / (kPassBThreads / kWave);
+  p->PB = (int)(bblocks < kPassBMaxBlocks ? bblocks : kPassBMaxBlocks);
   p->G2 = (p->PA + kReduceChunk - 1) / kReduceChunk;  // <= kMaxPartial2 since PA <= 512
   const int64_t rows = (s + 15) / 16;
   p->rpt = rows <= 4 ? 4 : rows <= 8 ? 8 : rows <= 12 ? 12 : rows <= 16 ? 16 : rows <= 24 ? 24 : 0;
@@ -61,7 +62,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
   p->off_tri = off;
   off = align256(off + tri);
   p->off_tri2 = off;
-  off = align256(off + tri);
+  off = align256(off + (size_t)p->nmax * p->nmax * sizeof(double));
   p->off_Rs = off;
   off = align256(off + (size_t)n * n * sizeof(double));
   p->off_part = off;
@@ -104,7 +105,7 @@ void launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
 
 template <int NMAX>
 void launch_pass_B(const Plan& p, const PassBArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_passB<NMAX>), dim3(p.PB), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL((k_passB<NMAX>), dim3(p.PB), dim3(kPassBThreads), 0, st, a);
 }
 
 // Event timing (rpcholqr_timing_*): one set of NSTAGES+1 events per recorded call.
@@ -191,7 +192,8 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pa.tri_s = tri;
   pa.partials = part;
   pa.info = inf;
-  pa.A1 = A1;
+  pa.W = Q;
+  pa.ldw = ldq;
   switch (p.nmax) {
     case 16: launch_passes_A<16>(p, pa, st); break;
     case 32: launch_passes_A<32>(p, pa, st); break;
@@ -200,6 +202,9 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
+  if (A1 && hipMemcpy2DAsync(A1, (size_t)m * sizeof(double), Q, (size_t)ldq * sizeof(double),
+                             (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return RPCHOLQR_EHIP;
 
   hipLaunchKernelGGL(k_reduce_partials, dim3((p.E + kReduceThreads - 1) / kReduceThreads, p.G2),
                      dim3(kReduceThreads), 0, st, (const double*)part, p.PA, p.E, part2, (const int32_t*)inf);
@@ -215,7 +220,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   ca.n = (int32_t)n;
   ca.nmax = p.nmax;
   ca.Rs = Rs_ws;
-  ca.tri2 = tri2;
+  ca.T2 = tri2;
   ca.R = R;
   ca.ldr = ldr;
   ca.info = inf;
@@ -229,10 +234,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   PassBArgs pb;
   pb.m = m;
   pb.n = (int32_t)n;
-  pb.A = A;
-  pb.lda = lda;
-  pb.tri_s = tri;
-  pb.tri_2 = tri2;
+  pb.T2 = tri2;
   pb.Q = Q;
   pb.ldq = ldq;
   pb.info = inf;

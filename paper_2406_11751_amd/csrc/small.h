@@ -8,8 +8,8 @@
 namespace rpq {
 
 constexpr int kReduceThreads = 256;
-constexpr int kReduceChunk = 32;  // partials summed per thread in the first level
-constexpr int kMaxPartial2 = 16;  // second-level partials (first-level chunks) at most
+constexpr int kReduceChunk = 64;  // partials summed per thread in the first level
+constexpr int kMaxPartial2 = 8;   // second-level partials (first-level chunks) at most
 constexpr int kCholThreads = 256;
 constexpr int kCholMaxN = 64;
 constexpr int kCholLdg = kCholMaxN + 1;
@@ -41,7 +41,7 @@ struct CholArgs {
   int32_t G2, E, NB;       // number of second-level partials, doubles per Gram, 16-blocks
   int32_t n, nmax;
   const double* Rs;     // R_s, n x n column-major
-  double* tri2;         // out: packed R2 for the row solves (see Tri)
+  double* T2;           // out: R2^{-1}, nmax x nmax row-major, zero outside the n x n upper triangle
   double* R;            // out: n x n, ld ldr
   int64_t ldr;
   int32_t* info;
@@ -51,13 +51,13 @@ struct CholArgs {
 
 // One workgroup.  The second-level partials are summed by all threads; the
 // Cholesky factorization runs in wave 0 with lane j holding column j of G1 in
-// registers (right-looking: at step k the pivot row is scaled by sqrt(G(k,k))
+// registers (right-looking: at step k the pivot row is scaled by 1/sqrt(G(k,k))
 // and broadcast through LDS, then every lane j updates G(i,j) -= R(k,i) R(k,j)
 // for i > k).  A non-positive or non-finite pivot gives ECHOL(k).
 __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
   __shared__ double G[kCholMaxN * kCholLdg];
   __shared__ double Rs_l[kCholMaxN * kCholLdg];  // R_s row-major
-  __shared__ double rowk[kCholMaxN];
+  __shared__ double rowk[2][kCholMaxN];
   __shared__ int bad_s;
   if (a.info[0] != 0) return;
   const int n = a.n, tid = threadIdx.x;
@@ -66,24 +66,33 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
   // Stage R_s for the R product and assemble G1 from the second-level
   // partials (independent loads first, then the sum in ascending g).
   for (int e = tid; e < n * n; e += kCholThreads) Rs_l[(e % n) * kCholLdg + e / n] = a.Rs[e];
-  for (int e = tid; e < a.E; e += kCholThreads) {
-    const int tile = e >> 8, w = e & 255;
-    int bi = 0, rem = tile;
-    while (rem >= a.NB - bi) {
-      rem -= a.NB - bi;
-      ++bi;
-    }
-    const int bj = bi + rem;
-    const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
-    if (i <= j && j < n) {
-      double v[kMaxPartial2];
+  constexpr int kEntries = 4;  // entries per thread per round: all their loads in flight together
+  for (int e0 = tid; e0 < a.E; e0 += kEntries * kCholThreads) {
+    double v[kEntries][kMaxPartial2];
 #pragma unroll
-      for (int g = 0; g < kMaxPartial2; ++g) v[g] = (g < a.G2) ? a.partial2[(int64_t)g * a.E + e] : 0.0;
-      double acc = v[0];
+    for (int u = 0; u < kEntries; ++u) {
+      const int e = e0 + u * kCholThreads;
+#pragma unroll
+      for (int g = 0; g < kMaxPartial2; ++g)
+        v[u][g] = (e < a.E && g < a.G2) ? a.partial2[(int64_t)g * a.E + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kEntries; ++u) {
+      const int e = e0 + u * kCholThreads;
+      if (e >= a.E) break;
+      const int tile = e >> 8, w = e & 255;
+      int bi = 0, rem = tile;
+      while (rem >= a.NB - bi) {
+        rem -= a.NB - bi;
+        ++bi;
+      }
+      const int bj = bi + rem;
+      const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
+      double acc = v[u][0];
 #pragma unroll
       for (int g = 1; g < kMaxPartial2; ++g)
-        if (g < a.G2) acc = acc + v[g];
-      G[i * kCholLdg + j] = acc;
+        if (g < a.G2) acc = acc + v[u][g];
+      if (i <= j && j < n) G[i * kCholLdg + j] = acc;
     }
   }
   __syncthreads();
@@ -109,12 +118,13 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
         break;
       }
       const double rkk = __builtin_sqrt(d);
-      g[k] = (lane == k) ? rkk : g[k] / rkk;
-      rowk[lane] = g[k];
-      wave_lds_fence();
+      const double rinv = 1.0 / rkk;
+      g[k] = (lane == k) ? rkk : g[k] * rinv;
+      // Row k of R2 to every lane through LDS (two buffers: the next step's
+      // write cannot overtake this step's reads of the same address).
+      rowk[k & 1][lane] = g[k];
 #pragma unroll
-      for (int i = k + 1; i < kCholMaxN; ++i) g[i] = __builtin_fma(-rowk[i], g[k], g[i]);
-      wave_lds_fence();
+      for (int i = k + 1; i < kCholMaxN; ++i) g[i] = __builtin_fma(-rowk[k & 1][i], g[k], g[i]);
     }
     // Write R2 back into G's upper triangle (lane j owns column j).
     if (lane < n) {
@@ -133,18 +143,6 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     return;
   }
 
-  // R2 for pass B (packed, identity padding) and the optional copy.
-  const int nmax = a.nmax;
-  for (int e = tid; e < nmax * nmax; e += kCholThreads) {
-    const int k = e / nmax, j = e - k * nmax;
-    if (j < k) continue;
-    double v;
-    if (k < n && j < n)
-      v = (j == k) ? 1.0 / G[k * kCholLdg + k] : G[k * kCholLdg + j];
-    else
-      v = (j == k) ? 1.0 : 0.0;
-    a.tri2[tri_row_start(k, nmax) + (j - k)] = v;
-  }
   if (a.R2_out) {
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
@@ -152,13 +150,46 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     }
   }
 
-  // Line 8: R = R2 R_s (upper times upper).
+  // T2 = R2^{-1} for pass B: lane i of wave 0 solves x R2 = e_i (row i of T2)
+  // with the row-wise substitution; R2 is read from LDS (broadcast).
+  const int nmax = a.nmax;
+  if (tid < kWave) {
+    const int lane = tid;
+    double x[kCholMaxN];
+#pragma unroll
+    for (int k = 0; k < kCholMaxN; ++k) x[k] = (k == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < kCholMaxN; ++k) {
+      if (k < n) {
+        x[k] = x[k] / G[k * kCholLdg + k];
+#pragma unroll
+        for (int j = k + 1; j < kCholMaxN; ++j)
+          if (j < n) x[j] = __builtin_fma(-x[k], G[k * kCholLdg + j], x[j]);
+      }
+    }
+    if (lane < nmax) {
+#pragma unroll
+      for (int j = 0; j < kCholMaxN; ++j)
+        if (j < nmax) a.T2[lane * nmax + j] = (lane < n && j < n && j >= lane) ? x[j] : 0.0;
+    }
+  }
+
+  // Line 8: R = R2 R_s (upper times upper).  Consecutive threads take
+  // consecutive j (R_s row reads are contiguous, R2 reads are broadcasts); four
+  // partial sums per entry.
   for (int e = tid; e < n * n; e += kCholThreads) {
-    const int i = e % n, j = e / n;
-    double acc = 0.0;
-    if (i <= j)
-      for (int k = i; k <= j; ++k) acc = __builtin_fma(G[i * kCholLdg + k], Rs_l[k * kCholLdg + j], acc);
-    a.R[i + (int64_t)j * a.ldr] = acc;
+    const int j = e % n, i = e / n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i <= j) {
+      for (int k0 = i; k0 <= j; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u;
+          if (k <= j) acc[u] = __builtin_fma(G[i * kCholLdg + k], Rs_l[k * kCholLdg + j], acc[u]);
+        }
+      }
+    }
+    a.R[i + (int64_t)j * a.ldr] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
 }
 
