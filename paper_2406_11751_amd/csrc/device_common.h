@@ -8,6 +8,11 @@ namespace rpq {
 
 constexpr int kWave = 64;
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8; a field at its maximum does not wait).
+constexpr int kWaitLgkm0 = 0xC07F;  // lgkmcnt(0) only
+constexpr int kWaitVm0 = 0x0F70;    // vmcnt(0) only
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter form: output number
@@ -72,13 +77,15 @@ struct Tri {
 // Each t_j receives its fma updates in ascending k, so the result equals the
 // substitution x_j = (t_j - sum_{k<j} x_k U(k,j)) * (1/U(j,j)) accumulated in
 // that order.  Padding columns j >= n never feed a column below n.
-// The triangle is consumed in groups of G values; the loads of group g+1 are
-// issued before the arithmetic of group g and a scheduling barrier closes each
-// group, so at most 2G triangle values are live in registers.  With SYNC > 0
-// the waves of the workgroup meet at a barrier every SYNC groups, so that they
-// sweep the triangle together and its values are fetched into the scalar cache
-// once per workgroup rather than once per wave (the caller must give every wave
-// of the workgroup the same number of calls).
+// The triangle is consumed in groups of G values.  At the top of group g the
+// wave waits for the values of group g (lgkmcnt(0): scalar loads return out of
+// order, so no finer wait exists), then issues the loads of group g+1 and does
+// the arithmetic of group g while they are in flight; a scheduling barrier
+// closes each group, so at most 2G triangle values are live in registers.
+// With SYNC > 0 the waves of the workgroup meet at a barrier every SYNC groups,
+// so that they sweep the triangle together and its values are fetched into the
+// scalar cache once per workgroup rather than once per wave (the caller must
+// give every wave of the workgroup the same number of calls).
 template <int NMAX, int G, int SYNC, typename P>
 __device__ __forceinline__ void trsm_row(double (&t)[NMAX], P tri) {
   constexpr Tri<NMAX> map{};
@@ -89,6 +96,8 @@ __device__ __forceinline__ void trsm_row(double (&t)[NMAX], P tri) {
   for (int i = 0; i < G; ++i) cur[i] = (i < S) ? tri[i] : 0.0;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int p = (g + 1) * G + i;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -24,6 +25,9 @@ constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles
 constexpr int kPassAMaxBlocks = 512;
 static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
 constexpr int kPassBMaxBlocks = 2048;
+// The LDS-staged ping-pong pass A (k_passA_pp) is built and tested but not the
+// default: on MI355X it measures slower than the register-load kernel.
+constexpr bool kStagedPassA = false;
 
 struct Plan {
   int nmax = 0, NB = 0, E = 0;
@@ -98,9 +102,38 @@ void launch_sketch(const Plan& p, const SketchArgs& a, hipStream_t st) {
   }
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < 64) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
+  return cus;
+}
+
+// Pass A launch: the LDS-staged kernel when columns are 16-byte aligned, with
+// one wave of work per SIMD slot the LDS allows; else the register kernel.
+// Returns the number of workgroups launched (= Gram partials written), 0 on error.
 template <int NMAX>
-void launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
+int launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
+  const bool aligned = ((uintptr_t)a.A % 16 == 0) && (a.lda % 2 == 0);
+  const int cus = kStagedPassA ? device_cus() : 0;
+  if (kStagedPassA && aligned && cus > 0) {
+    const int64_t pgroups = (p.panels + kPPWaves - 1) / kPPWaves;
+    const int64_t slots = (int64_t)cus * PassAPP<NMAX>::OCC;
+    int64_t grid = pgroups < slots ? pgroups : slots;
+    if (grid > p.PA) grid = p.PA;
+    hipLaunchKernelGGL((k_passA_pp<NMAX>), dim3((unsigned)grid), dim3(kPPThreads), 0, st, a);
+    return (int)grid;
+  }
   hipLaunchKernelGGL((k_passA_mfma<NMAX>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  return p.PA;
 }
 
 template <int NMAX>
@@ -155,7 +188,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   hipEvent_t* ev = timing_slot();
   int stage = 0;
   auto mark = [&]() {
-    if (ev) hipEventRecord(ev[stage++], st);
+    if (ev) (void)hipEventRecord(ev[stage++], st);
   };
   mark();
 
@@ -194,27 +227,29 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pa.info = inf;
   pa.W = Q;
   pa.ldw = ldq;
+  int pa_grid = 0;
   switch (p.nmax) {
-    case 16: launch_passes_A<16>(p, pa, st); break;
-    case 32: launch_passes_A<32>(p, pa, st); break;
-    case 48: launch_passes_A<48>(p, pa, st); break;
-    default: launch_passes_A<64>(p, pa, st); break;
+    case 16: pa_grid = launch_passes_A<16>(p, pa, st); break;
+    case 32: pa_grid = launch_passes_A<32>(p, pa, st); break;
+    case 48: pa_grid = launch_passes_A<48>(p, pa, st); break;
+    default: pa_grid = launch_passes_A<64>(p, pa, st); break;
   }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  const int g2 = (pa_grid + kReduceChunk - 1) / kReduceChunk;  // <= p.G2
   mark();
   if (A1 && hipMemcpy2DAsync(A1, (size_t)m * sizeof(double), Q, (size_t)ldq * sizeof(double),
                              (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return RPCHOLQR_EHIP;
 
-  hipLaunchKernelGGL(k_reduce_partials, dim3((p.E + kReduceThreads - 1) / kReduceThreads, p.G2),
-                     dim3(kReduceThreads), 0, st, (const double*)part, p.PA, p.E, part2, (const int32_t*)inf);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((p.E + kReduceThreads - 1) / kReduceThreads, g2),
+                     dim3(kReduceThreads), 0, st, (const double*)part, pa_grid, p.E, part2, (const int32_t*)inf);
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
   // Lines 5-6 (Cholesky) and 8 (R = R2 R_s).
   CholArgs ca;
   ca.partial2 = part2;
-  ca.G2 = p.G2;
+  ca.G2 = g2;
   ca.E = p.E;
   ca.NB = p.NB;
   ca.n = (int32_t)n;
@@ -226,7 +261,12 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   ca.info = inf;
   ca.G1_out = G1;
   ca.R2_out = R2;
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCholThreads), 0, st, ca);
+  switch (p.nmax) {
+    case 16: hipLaunchKernelGGL((k_cholesky<16>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
+    case 32: hipLaunchKernelGGL((k_cholesky<32>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
+    case 48: hipLaunchKernelGGL((k_cholesky<48>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
+    default: hipLaunchKernelGGL((k_cholesky<64>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
+  }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 

@@ -12,7 +12,6 @@ constexpr int kReduceChunk = 64;  // partials summed per thread in the first lev
 constexpr int kMaxPartial2 = 8;   // second-level partials (first-level chunks) at most
 constexpr int kCholThreads = 256;
 constexpr int kCholMaxN = 64;
-constexpr int kCholLdg = kCholMaxN + 1;
 
 // First level: partial2[g][e] = sum of partials[p][e] over p in chunk g, in
 // ascending p.  Grid: (ceil(E/256), ceil(P/kReduceChunk)).
@@ -49,147 +48,248 @@ struct CholArgs {
   double* R2_out;       // optional n x n, ld n
 };
 
-// One workgroup.  The second-level partials are summed by all threads; the
-// Cholesky factorization runs in wave 0 with lane j holding column j of G1 in
-// registers (right-looking: at step k the pivot row is scaled by 1/sqrt(G(k,k))
-// and broadcast through LDS, then every lane j updates G(i,j) -= R(k,i) R(k,j)
-// for i > k).  A non-positive or non-finite pivot gives ECHOL(k).
-__global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
-  __shared__ double G[kCholMaxN * kCholLdg];
-  __shared__ double Rs_l[kCholMaxN * kCholLdg];  // R_s row-major
-  __shared__ double rowk[2][kCholMaxN];
+// Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
+// four waves, NMAX/16 column blocks of 16.  All matrices are staged in LDS
+// row-major with row stride kCLd.  Per block kb:
+//   (a) wave 0 factors the 16x16 diagonal block and inverts it in the same
+//       sweep: lanes 0-15 hold the columns of the block, lanes 16-31 the rows of
+//       the identity; step k scales register k by 1/R(k,k) (lane k gets R(k,k))
+//       and broadcasts R(k,i), i > k, by readlane; one fma per register then
+//       updates both the trailing columns and the inverse rows;
+//   (b) panel R(kb, j) = R(kb,kb)^{-T} G(kb, j), one MFMA block product per j;
+//   (c) trailing update G(i, j) -= R(kb,i)^T R(kb,j) on MFMA.
+// The off-diagonal blocks of R2^{-1} follow by block back substitution
+// T(i,j) = -T(i,i) sum_{i<l<=j} R2(i,l) T(l,j), by increasing j - i, and
+// R = R2 R_s is a sum of MFMA block products.  Diagonal pivots use the
+// hardware reciprocal square root refined by Newton steps.
+// A non-positive or non-finite pivot gives ECHOL at its column.
+constexpr int kCLd = kCholMaxN + 1;
+
+// v_mfma_f64_16x16x4f64 operand and result positions within a 16x16 block:
+//   A(i, kk): lane l holds i = l%16, kk = l/16;  B(kk, j): kk = l/16, j = l%16;
+//   D(i, j):  lane l register v holds i = 4v + l/16, j = l%16.
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// A operand, chunk c, of the block at (r0, c0) of row-major M.
+__device__ __forceinline__ double opA(const double* M, int r0, int c0, int c, int lane) {
+  return M[(r0 + (lane & 15)) * kCLd + c0 + 4 * c + (lane >> 4)];
+}
+// A operand, chunk c, of the transpose of the block at (r0, c0).
+__device__ __forceinline__ double opAT(const double* M, int r0, int c0, int c, int lane) {
+  return M[(r0 + 4 * c + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+}
+// B operand, chunk c, of the block at (r0, c0).
+__device__ __forceinline__ double opB(const double* M, int r0, int c0, int c, int lane) {
+  return M[(r0 + 4 * c + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+}
+__device__ __forceinline__ d4 load_d(const double* M, int r0, int c0, int lane) {
+  d4 x;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[v] = M[(r0 + 4 * v + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+  return x;
+}
+__device__ __forceinline__ void store_d(double* M, int r0, int c0, int lane, d4 x) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) M[(r0 + 4 * v + (lane >> 4)) * kCLd + c0 + (lane & 15)] = x[v];
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
+  constexpr int NB = NMAX / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int E = NT * 256;
+  constexpr int PER = (E + kCholThreads - 1) / kCholThreads;  // Gram entries per thread
+  static_assert(NMAX % 16 == 0 && NMAX <= kCholMaxN, "block size");
+  __shared__ double Gs[kCholMaxN * kCLd];   // G1, then R2 (upper)
+  __shared__ double Ts[kCholMaxN * kCLd];   // R2^{-1} (upper)
+  __shared__ double Rsl[kCholMaxN * kCLd];  // R_s
   __shared__ int bad_s;
   if (a.info[0] != 0) return;
-  const int n = a.n, tid = threadIdx.x;
+  const int n = a.n, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   if (tid == 0) bad_s = -1;
 
-  // Stage R_s for the R product and assemble G1 from the second-level
-  // partials (independent loads first, then the sum in ascending g).
-  for (int e = tid; e < n * n; e += kCholThreads) Rs_l[(e % n) * kCholLdg + e / n] = a.Rs[e];
-  constexpr int kEntries = 4;  // entries per thread per round: all their loads in flight together
-  for (int e0 = tid; e0 < a.E; e0 += kEntries * kCholThreads) {
-    double v[kEntries][kMaxPartial2];
+  // Assemble G1 (upper; identity beyond n) from the second-level partials:
+  // every load first, then the sums in ascending partial index.  Zero the
+  // lower triangles so that diagonal-block products see triangular operands.
+  {
+    double v[PER][kMaxPartial2];
 #pragma unroll
-    for (int u = 0; u < kEntries; ++u) {
-      const int e = e0 + u * kCholThreads;
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kCholThreads;
 #pragma unroll
       for (int g = 0; g < kMaxPartial2; ++g)
-        v[u][g] = (e < a.E && g < a.G2) ? a.partial2[(int64_t)g * a.E + e] : 0.0;
+        v[u][g] = (e < E && g < a.G2) ? a.partial2[(int64_t)g * E + e] : 0.0;
+    }
+    for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
+      const int i = e / NMAX, j = e % NMAX;
+      Rsl[i * kCLd + j] = (i <= j && j < n) ? a.Rs[i + j * n] : 0.0;
+      Ts[i * kCLd + j] = 0.0;
+      if (i > j) Gs[i * kCLd + j] = 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kEntries; ++u) {
-      const int e = e0 + u * kCholThreads;
-      if (e >= a.E) break;
-      const int tile = e >> 8, w = e & 255;
-      int bi = 0, rem = tile;
-      while (rem >= a.NB - bi) {
-        rem -= a.NB - bi;
-        ++bi;
-      }
-      const int bj = bi + rem;
-      const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
-      double acc = v[u][0];
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * kCholThreads;
+      if (e < E) {
+        const int tile = e >> 8, w = e & 255;
+        int bi = 0, rem = tile;
 #pragma unroll
-      for (int g = 1; g < kMaxPartial2; ++g)
-        if (g < a.G2) acc = acc + v[u][g];
-      if (i <= j && j < n) G[i * kCholLdg + j] = acc;
+        for (int b = 0; b < NB; ++b)
+          if (rem >= NB - bi) {
+            rem -= NB - bi;
+            ++bi;
+          }
+        const int bj = bi + rem;
+        const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
+        double acc = v[u][0];
+#pragma unroll
+        for (int g = 1; g < kMaxPartial2; ++g)
+          if (g < a.G2) acc = acc + v[u][g];
+        if (i <= j) Gs[i * kCLd + j] = (j < n) ? acc : (i == j ? 1.0 : 0.0);
+      }
     }
   }
   __syncthreads();
   if (a.G1_out) {
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
-      a.G1_out[e] = (i <= j) ? G[i * kCholLdg + j] : 0.0;
+      a.G1_out[e] = (i <= j) ? Gs[i * kCLd + j] : 0.0;
     }
   }
 
-  if (tid < kWave) {
-    const int lane = tid;
-    double g[kCholMaxN];
 #pragma unroll
-    for (int i = 0; i < kCholMaxN; ++i) g[i] = (i <= lane && lane < n) ? G[i * kCholLdg + lane] : 0.0;
-    int bad = -1;
+  for (int kb = 0; kb < NB; ++kb) {
+    const int base = 16 * kb;
+    // (a) diagonal block: factor (lanes 0-15) and invert (lanes 16-31).
+    if (wave == 0) {
+      double g[16];
 #pragma unroll
-    for (int k = 0; k < kCholMaxN; ++k) {
-      if (k >= n || bad >= 0) break;
-      const double d = readlane_d(g[k], k);
-      if (!(d > 0.0) || !__builtin_isfinite(d)) {
-        bad = k;
-        break;
+      for (int r = 0; r < 16; ++r)
+        g[r] = (lane < 16) ? Gs[(base + r) * kCLd + base + lane] : (lane - 16 == r ? 1.0 : 0.0);
+      int bad = -1;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (bad < 0) {
+          const double d = readlane_d(g[k], k);
+          if (!(d > 0.0) || !__builtin_isfinite(d)) {
+            bad = base + k;
+          } else {
+            // Coupled Newton iteration for sqrt(d) and 1/sqrt(d) from the
+            // hardware estimate (two steps), then a residual correction.
+            const double y0 = __builtin_amdgcn_rsq(d);
+            double gq = d * y0, hq = 0.5 * y0;
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+              const double rr = __builtin_fma(-hq, gq, 0.5);
+              gq = __builtin_fma(gq, rr, gq);
+              hq = __builtin_fma(hq, rr, hq);
+            }
+            const double rkk = __builtin_fma(__builtin_fma(-gq, gq, d), hq, gq);  // R(k,k)
+            const double y = 2.0 * hq;                                           // 1 / R(k,k)
+            g[k] = (lane == k) ? rkk : g[k] * y;
+#pragma unroll
+            for (int i = k + 1; i < 16; ++i) g[i] = __builtin_fma(-readlane_d(g[k], i), g[k], g[i]);
+          }
+        }
       }
-      const double rkk = __builtin_sqrt(d);
-      const double rinv = 1.0 / rkk;
-      g[k] = (lane == k) ? rkk : g[k] * rinv;
-      // Row k of R2 to every lane through LDS (two buffers: the next step's
-      // write cannot overtake this step's reads of the same address).
-      rowk[k & 1][lane] = g[k];
+      if (lane < 16) {
 #pragma unroll
-      for (int i = k + 1; i < kCholMaxN; ++i) g[i] = __builtin_fma(-rowk[k & 1][i], g[k], g[i]);
-    }
-    // Write R2 back into G's upper triangle (lane j owns column j).
-    if (lane < n) {
+        for (int r = 0; r < 16; ++r) Gs[(base + r) * kCLd + base + lane] = (r <= lane) ? g[r] : 0.0;
+      } else if (lane < 32) {
 #pragma unroll
-      for (int i = 0; i < kCholMaxN; ++i)
-        if (i <= lane) G[i * kCholLdg + lane] = g[i];
+        for (int c = 0; c < 16; ++c) Ts[(base + lane - 16) * kCLd + base + c] = (c >= lane - 16) ? g[c] : 0.0;
+      }
+      if (lane == 0 && bad >= 0 && bad < n) bad_s = bad;
     }
-    if (lane == 0) bad_s = bad;
+    __syncthreads();
+    if (bad_s >= 0) {
+      if (tid == 0) {
+        a.info[0] = 2;
+        a.info[1] = bad_s;
+      }
+      return;
+    }
+    if (kb + 1 < NB) {
+      // (b) panel: R(kb, bj) = T(kb,kb)^T G(kb, bj).
+      if (wave < NB - 1 - kb) {
+        const int c0 = base + 16 + 16 * wave;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = mfma16(opAT(Ts, base, base, c, lane), opB(Gs, base, c0, c, lane), acc);
+        store_d(Gs, base, c0, lane, acc);
+      }
+      __syncthreads();
+      // (c) trailing update of the blocks (bi, bj), kb < bi <= bj.
+      int q = 0;
+#pragma unroll
+      for (int bi = kb + 1; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj) {
+          if (q % 4 == wave) {
+            d4 acc = load_d(Gs, 16 * bi, 16 * bj, lane);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc = mfma16(-opAT(Gs, base, 16 * bi, c, lane), opB(Gs, base, 16 * bj, c, lane), acc);
+            store_d(Gs, 16 * bi, 16 * bj, lane, acc);
+          }
+          ++q;
+        }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  if (bad_s >= 0) {
-    if (tid == 0) {
-      a.info[0] = 2;
-      a.info[1] = bad_s;
+
+  // Off-diagonal blocks of T = R2^{-1}, by increasing distance from the diagonal.
+#pragma unroll
+  for (int dist = 1; dist < NB; ++dist) {
+    const int bi = wave, bj = wave + dist;
+    if (bj < NB) {
+      d4 p = {0.0, 0.0, 0.0, 0.0};
+      for (int l = bi + 1; l <= bj; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p = mfma16(opA(Gs, 16 * bi, 16 * l, c, lane), opB(Ts, 16 * l, 16 * bj, c, lane), p);
+      d4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t = mfma16(-opA(Ts, 16 * bi, 16 * bi, c, lane), p[c], t);
+      store_d(Ts, 16 * bi, 16 * bj, lane, t);
     }
-    return;
+    __syncthreads();
   }
 
   if (a.R2_out) {
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
-      a.R2_out[e] = (i <= j) ? G[i * kCholLdg + j] : 0.0;
+      a.R2_out[e] = (i <= j) ? Gs[i * kCLd + j] : 0.0;
     }
   }
-
-  // T2 = R2^{-1} for pass B: lane i of wave 0 solves x R2 = e_i (row i of T2)
-  // with the row-wise substitution; R2 is read from LDS (broadcast).
-  const int nmax = a.nmax;
-  if (tid < kWave) {
-    const int lane = tid;
-    double x[kCholMaxN];
-#pragma unroll
-    for (int k = 0; k < kCholMaxN; ++k) x[k] = (k == lane) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < kCholMaxN; ++k) {
-      if (k < n) {
-        x[k] = x[k] / G[k * kCholLdg + k];
-#pragma unroll
-        for (int j = k + 1; j < kCholMaxN; ++j)
-          if (j < n) x[j] = __builtin_fma(-x[k], G[k * kCholLdg + j], x[j]);
-      }
-    }
-    if (lane < nmax) {
-#pragma unroll
-      for (int j = 0; j < kCholMaxN; ++j)
-        if (j < nmax) a.T2[lane * nmax + j] = (lane < n && j < n && j >= lane) ? x[j] : 0.0;
-    }
+  // T2 for pass B: NMAX x NMAX row-major, zero outside the n x n upper triangle.
+  for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
+    const int i = e / NMAX, j = e % NMAX;
+    a.T2[e] = (j >= i && j < n) ? Ts[i * kCLd + j] : 0.0;
   }
-
-  // Line 8: R = R2 R_s (upper times upper).  Consecutive threads take
-  // consecutive j (R_s row reads are contiguous, R2 reads are broadcasts); four
-  // partial sums per entry.
-  for (int e = tid; e < n * n; e += kCholThreads) {
-    const int j = e % n, i = e / n;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i <= j) {
-      for (int k0 = i; k0 <= j; k0 += 4) {
+  // Line 8: R = R2 R_s, upper block tiles on MFMA; blocks below the diagonal are zero.
+  {
+    int q = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u;
-          if (k <= j) acc[u] = __builtin_fma(G[i * kCholLdg + k], Rs_l[k * kCholLdg + j], acc[u]);
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+      for (int bj = bi; bj < NB; ++bj) {
+        if (q % 4 == wave) {
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int l = bi; l <= bj; ++l)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = mfma16(opA(Gs, 16 * bi, 16 * l, c, lane), opB(Rsl, 16 * l, 16 * bj, c, lane), acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * bi + 4 * v + (lane >> 4), j = 16 * bj + (lane & 15);
+            if (i < n && j < n) a.R[i + (int64_t)j * a.ldr] = acc[v];
+          }
         }
+        ++q;
       }
+    for (int e = tid; e < n * n; e += kCholThreads) {
+      const int i = e % n, j = e / n;
+      if (i / 16 > j / 16) a.R[i + (int64_t)j * a.ldr] = 0.0;
     }
-    a.R[i + (int64_t)j * a.ldr] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
 }
 

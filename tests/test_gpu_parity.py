@@ -116,13 +116,16 @@ def test_deterministic_bits():
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
-def test_leading_dimensions():
+@pytest.mark.parametrize("pad,off", [(13, 0), (14, 0), (14, 1)])
+def test_leading_dimensions(pad, off):
+    # Even lda with a 16-byte aligned A takes the LDS-staged pass A; an odd lda or
+    # an A that starts 8 bytes into an allocation takes the register-load kernel.
     m, n, s = 3001, 24, 72
     A_h = gen_usv(m, n, 1e6, 4)
-    announce("padded leading dimensions")
-    big = torch.full((n, m + 13), float("nan"), dtype=torch.float64, device="cuda").t()
-    big[:m] = dev(A_h)
-    A = big[:m]                                     # lda = m + 13
+    announce(f"padded leading dimensions pad={pad} off={off}")
+    big = torch.full((n, m + pad), float("nan"), dtype=torch.float64, device="cuda").t()
+    big[off:off + m] = dev(A_h)
+    A = big[off:off + m]                            # lda = m + pad
     Q = torch.zeros((n, m + 5), dtype=torch.float64, device="cuda").t()[:m]
     R = torch.zeros((n + 3, n + 3), dtype=torch.float64, device="cuda").t()[:n, :n]
     rq().factor(A, s, 9, Q=Q, R=R)
