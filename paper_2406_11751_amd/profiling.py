@@ -1,0 +1,140 @@
+"""Summaries of rocprofv3 runs of the library's kernels.
+
+Reads the CSV output of
+  rocprofv3 --kernel-trace --stats --output-format csv ...   (kernel statistics)
+  rocprofv3 --pmc FETCH_SIZE --output-format csv ...          (HBM bytes read)
+  rocprofv3 --pmc WRITE_SIZE --output-format csv ...          (HBM bytes written)
+and the same two counters taken on a plain device copy of known size
+(`python bench.py --copy-calibration`), which fixes the factor between what the
+counters report and the bytes that actually moved.  Writes a Markdown summary
+and a JSON record of the traffic of one kernel, stamped with a digest of the
+kernel sources so that a later change to them invalidates the record.
+
+    python -m paper_2406_11751_amd.profiling --stats DIR --fetch DIR --write DIR \\
+        --copy-fetch DIR --copy-write DIR --kernel k_passA --tag passA_fp64_1e6x64 \\
+        --workload "..." --command-stats "..." --command-fetch "..." ... --out profiles
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+# Sources that define the streaming-pass kernels (their traffic records go stale
+# when these change).
+KERNEL_SOURCES = ("csrc/passes.h", "csrc/device_common.h")
+COPY_BYTES = 64 * 1024 * 1024 * 8  # the calibration copy moves 512 MiB each way per call
+
+
+def source_digest(files=KERNEL_SOURCES) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(PKG, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _one(pattern: str, root: str) -> str:
+    hits = sorted(glob.glob(os.path.join(root, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {root}")
+    return hits[0]
+
+
+def kernel_stats(root: str):
+    rows = list(csv.DictReader(open(_one("*kernel_stats.csv", root))))
+    out = []
+    for r in rows:
+        out.append(dict(name=r["Name"], calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
+                        min_us=float(r["MinNs"]) / 1e3, max_us=float(r["MaxNs"]) / 1e3))
+    return out
+
+
+def counter_per_dispatch(root: str, counter: str):
+    """{kernel name: (dispatches, counter summed over a dispatch, averaged over dispatches)}."""
+    rows = list(csv.DictReader(open(_one("*counter_collection.csv", root))))
+    total = collections.defaultdict(float)
+    ids = collections.defaultdict(set)
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        total[r["Kernel_Name"]] += float(r["Counter_Value"])
+        ids[r["Kernel_Name"]].add(r["Dispatch_Id"])
+    return {k: (len(ids[k]), total[k] / len(ids[k])) for k in total}
+
+
+def _pick(table: dict, needle: str):
+    keys = [k for k in table if needle in k]
+    if not keys:
+        raise KeyError(f"no kernel matching {needle!r}")
+    return keys[0], table[keys[0]]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--kernel", required=True, help="substring of the kernel to record traffic for")
+    ap.add_argument("--copy-kernel", default="copyBuffer", help="substring of the calibration copy kernel")
+    ap.add_argument("--tag", required=True, help="file stem, named for the kernel and workload")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command-stats", required=True)
+    ap.add_argument("--command-fetch", required=True)
+    ap.add_argument("--command-write", required=True)
+    ap.add_argument("--command-copy", required=True)
+    ap.add_argument("--algorithmic-bytes", type=float, required=True,
+                    help="bytes the kernel must move per launch (for comparison)")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+
+    stats = kernel_stats(a.stats)
+    lib = [s for s in stats if "rpq::" in s["name"]]
+    fetch = counter_per_dispatch(a.fetch, "FETCH_SIZE")
+    write = counter_per_dispatch(a.write, "WRITE_SIZE")
+    cfetch = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE")
+    cwrite = counter_per_dispatch(a.copy_write, "WRITE_SIZE")
+    kname, (nf, f_kib) = _pick(fetch, a.kernel)
+    _, (nw, w_kib) = _pick(write, a.kernel)
+    _, (_, cf_kib) = _pick(cfetch, a.copy_kernel)
+    _, (_, cw_kib) = _pick(cwrite, a.copy_kernel)
+    fetch_scale = COPY_BYTES / (cf_kib * 1024.0)
+    write_scale = COPY_BYTES / (cw_kib * 1024.0)
+    traffic = f_kib * 1024.0 * fetch_scale + w_kib * 1024.0 * write_scale
+    rec = dict(kernel=kname, workload=a.workload, fetch_kib_per_dispatch=f_kib, write_kib_per_dispatch=w_kib,
+               dispatches=dict(fetch=nf, write=nw), copy_fetch_kib=cf_kib, copy_write_kib=cw_kib,
+               copy_bytes=COPY_BYTES, fetch_scale=fetch_scale, write_scale=write_scale,
+               traffic_bytes=traffic, algorithmic_bytes=a.algorithmic_bytes,
+               source_digest=source_digest(), sources=list(KERNEL_SOURCES))
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, f"traffic_{a.tag}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [f"# rocprofv3: {a.workload}", "",
+             "Kernel statistics, command (repository root, MI355X):", "", "```", a.command_stats, "```", "",
+             "| kernel | calls | average us | min us | max us |", "|---|---|---|---|---|"]
+    for s in sorted(lib, key=lambda s: -s["avg_us"] * s["calls"]):
+        lines.append(f"| `{s['name']}` | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | {s['max_us']:.1f} |")
+    lines += ["", f"HBM traffic of `{kname}` per dispatch (`FETCH_SIZE`, `WRITE_SIZE` in KiB), commands:", "",
+              "```", a.command_fetch, a.command_write, a.command_copy, "```", "",
+              "| quantity | value |", "|---|---|",
+              f"| FETCH_SIZE per dispatch | {f_kib:.0f} KiB |",
+              f"| WRITE_SIZE per dispatch | {w_kib:.0f} KiB |",
+              f"| plain copy of {COPY_BYTES >> 20} MiB: FETCH_SIZE / WRITE_SIZE | {cf_kib:.0f} / {cw_kib:.0f} KiB |",
+              f"| scale factors (bytes per counted byte) read / write | {fetch_scale:.3f} / {write_scale:.3f} |",
+              f"| traffic per dispatch (scaled) | {traffic / 1e6:.1f} MB |",
+              f"| algorithmic bytes per dispatch | {a.algorithmic_bytes / 1e6:.1f} MB |",
+              f"| kernel source digest | `{rec['source_digest']}` |", ""]
+    with open(os.path.join(a.out, f"{a.tag}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
