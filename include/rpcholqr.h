@@ -30,8 +30,9 @@
  *    argument and launch problems (rpcholqr_status).  Numerical failures are
  *    written to the device rpcholqr_info the caller passes; read it after
  *    synchronizing the stream.  On a numerical failure Q and R are unspecified.
- *  - A is read only.  Q must not overlap A (A is read twice), R must not
- *    overlap A or Q.  The strictly lower triangle of R is written as zero.
+ *  - A is read only.  Q must not overlap A (Q holds A1 = A R_s^{-1} while A
+ *    is still being read), R must not overlap A or Q.  The strictly lower
+ *    triangle of R is written as zero.
  */
 #ifndef RPCHOLQR_H
 #define RPCHOLQR_H
