@@ -116,7 +116,7 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
  * factor call records an event on its stream before the first kernel and after
  * each of its NSTAGES kernels (in order: sketch = sample + gather + sketch QR,
  * pass A = A1 and Gram partials, reduce = partial Gram sum, cholesky =
- * Cholesky + R product, pass B = A1 again and Q).  No device memory is
+ * Cholesky, R2^{-1} and R product, pass B = Q = A1 R2^{-1} in place).  No device memory is
  * allocated.  Process-wide state: do not time calls from several host threads
  * at once.
  *   rpcholqr_timing_enable(1) starts recording (and discards earlier records),
@@ -128,6 +128,53 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
 #define RPCHOLQR_NSTAGES 5
 int32_t rpcholqr_timing_enable(int32_t on);
 int32_t rpcholqr_timing_read(double* ms, int32_t count);
+
+/* Batched factorization: many independent problems, one plan.  Not in the
+ * paper; the use it serves is the one Section 1 motivates Cholesky-QR with,
+ * block methods (block Krylov, LOBPCG) that need many thin QRs of modest size.
+ * Each problem b is factored with exactly the arithmetic of rpcholqr_factor
+ * (same sampling, sketch, row solves and info semantics); only the number of
+ * row blocks over which the Gram matrix is partially summed differs, so Q and
+ * R agree with rpcholqr_factor to rounding (about 1e-15).
+ *
+ * rpcholqr_batched_plan_create
+ *   batch          number of problems (>= 1)
+ *   m, n, s, seed, lda, ldq, ldr
+ *                  HOST arrays of length batch, per problem as in
+ *                  rpcholqr_factor (1 <= n <= rpcholqr_max_n(), s <= 1536)
+ *   A, Q, R        HOST arrays of length batch holding DEVICE pointers; within
+ *                  a problem Q must not overlap A, R must not overlap A or Q;
+ *                  different problems must not share Q or R memory
+ *   precision      rpcholqr_precision
+ *   plan           receives the plan
+ *   bad_problem    optional; receives the index of the first invalid problem
+ *                  (-1 if none)
+ *   Validates every problem (EINVAL / EUNSUPPORTED), allocates the plan's device
+ *   memory on the current device (descriptor tables and one workspace per
+ *   problem, rpcholqr_batched_plan_device_bytes) and uploads the tables with
+ *   blocking copies.  The plan refers to the caller's A, Q and R, which must
+ *   stay valid while it is executed.
+ * rpcholqr_batched_execute
+ *   Launches every problem on `stream` (hipStream_t as void*): one launch per
+ *   stage and size class, no allocation and no host-to-device copy, so a
+ *   stream capture into a HIP graph records it.  info is a DEVICE array of
+ *   batch rpcholqr_info, one per problem.  Executions of the same plan must not
+ *   overlap (they share its workspace).
+ * rpcholqr_batched_plan_destroy frees the plan; the caller first waits for the
+ *   work that uses it.
+ * rpcholqr_factor_batched is create + execute + stream synchronize + destroy. */
+typedef struct rpcholqr_batched_plan rpcholqr_batched_plan;
+int32_t rpcholqr_batched_plan_create(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,
+                                     const uint64_t* seed, const double* const* A, const int64_t* lda,
+                                     double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,
+                                     int32_t precision, rpcholqr_batched_plan** plan, int64_t* bad_problem);
+int32_t rpcholqr_batched_execute(const rpcholqr_batched_plan* plan, rpcholqr_info* info, void* stream);
+size_t rpcholqr_batched_plan_device_bytes(const rpcholqr_batched_plan* plan);
+int32_t rpcholqr_batched_plan_destroy(rpcholqr_batched_plan* plan);
+int32_t rpcholqr_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,
+                                const uint64_t* seed, const double* const* A, const int64_t* lda,
+                                double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,
+                                int32_t precision, rpcholqr_info* info, void* stream, int64_t* bad_problem);
 
 #ifdef __cplusplus
 }

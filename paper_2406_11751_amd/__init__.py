@@ -4,5 +4,6 @@ Garrison & Ipsen, "A randomized preconditioned Cholesky-QR algorithm"
 (arXiv 2406.11751).  The computation lives in HIP kernels behind the C ABI of
 include/rpcholqr.h; this package only builds and binds that library.
 """
-from .native import (FP64, FP32_REFINE, BF16X2_REFINE, RpCholQRError, colmajor_empty, factor,  # noqa: F401
-                     load_library, max_n, timing_enable, timing_read, workspace_bytes)
+from .native import (FP64, FP32_REFINE, BF16X2_REFINE, BatchedPlan, RpCholQRError, colmajor_empty,  # noqa: F401
+                     factor, factor_batched, load_library, max_n, timing_enable, timing_read,
+                     workspace_bytes)

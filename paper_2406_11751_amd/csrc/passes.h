@@ -64,12 +64,12 @@ struct PassAArgs {
 
 // Final cross-wave sum: each wave stored its tiles in LDS red[wave][E].
 template <int E>
-__device__ __forceinline__ void sum_waves_to_partial(const double* red, double* __restrict__ out) {
+__device__ __forceinline__ void sum_waves_to_partial(const double* red, double* __restrict__ out, int bid) {
   for (int e = threadIdx.x; e < E; e += kPassThreads) {
     double v = red[e];
 #pragma unroll
     for (int w = 1; w < kPassWaves; ++w) v = v + red[w * E + e];
-    out[(int64_t)blockIdx.x * E + e] = v;
+    out[(int64_t)bid * E + e] = v;
   }
 }
 
@@ -90,7 +90,7 @@ __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[N
 // pass A (NMAX a multiple of 16, <= 64).
 // LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 doubles.
 template <int NMAX>
-__global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
+__device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk) {
   static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA Gram tiles");
   constexpr int NB = GramShape<NMAX>::NB, NT = GramShape<NMAX>::NT, E = GramShape<NMAX>::E;
   constexpr int LDX = NMAX + 1;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
   const int half_row = lane & 31;
   const int rq = lane >> 4, cq = lane & 15;  // MFMA operand position
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-  for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
+  for (int64_t pg = bid; pg < pgroups; pg += nblk) {
     const int64_t r0 = (pg * kPassWaves + wave) * kWave;
     const bool valid = r0 + lane < a.m;
     double t[NMAX];
@@ -154,7 +154,12 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
       lds[wave * E + q * 256 + i * 16 + j] = acc[q][v];
     }
   __syncthreads();
-  sum_waves_to_partial<E>(lds, a.partials);
+  sum_waves_to_partial<E>(lds, a.partials, bid);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
+  passA_body<NMAX>(a, blockIdx.x, gridDim.x);
 }
 
 // pass A, LDS-staged ping-pong (NMAX a multiple of 16, <= 64; columns 16-byte
@@ -366,7 +371,7 @@ constexpr int kPassBThreads = 256;
 //                       stored as four 128-byte column segments per store.
 // All loads of a block are issued before its stores, so the update is in place.
 template <int NMAX>
-__global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
+__device__ __forceinline__ void passB_body(const PassBArgs& a, int bid, int nblk) {
   static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA tiles");
   constexpr int NB = NMAX / 16, NKC = NMAX / 4;
   constexpr int NOPS = NKC * NB - 2 * NB * (NB - 1);  // (kc, cb) pairs with cb >= kc / 4
@@ -382,8 +387,8 @@ __global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
       for (int cb = kc / 4; cb < NB; ++cb) t2[o++] = a.T2[(4 * kc + g4) * NMAX + 16 * cb + i16];
   }
   const int64_t blocks = (a.m + 15) / 16;
-  const int64_t nw = (int64_t)gridDim.x * (kPassBThreads / kWave);
-  for (int64_t blk = (int64_t)blockIdx.x * (kPassBThreads / kWave) + wave; blk < blocks; blk += nw) {
+  const int64_t nw = (int64_t)nblk * (kPassBThreads / kWave);
+  for (int64_t blk = (int64_t)bid * (kPassBThreads / kWave) + wave; blk < blocks; blk += nw) {
     const int64_t row = blk * 16 + i16;
     const bool rvalid = row < a.m;
     double x[NKC];
@@ -413,6 +418,11 @@ __global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
         }
     }
   }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
+  passB_body<NMAX>(a, blockIdx.x, gridDim.x);
 }
 
 }  // namespace rpq

@@ -4,8 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <atomic>
+#include <map>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -15,6 +17,7 @@
 #include "passes.h"
 #include "sketch.h"
 #include "small.h"
+#include "batched.h"
 
 namespace {
 
@@ -47,17 +50,21 @@ int pick_nmax(int64_t n) {
   return 64;
 }
 
-bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
+// Workspace layout of one problem.  pa_cap bounds the number of pass-A
+// workgroups (= Gram partials).  With direct_partials the Cholesky kernel sums
+// the partials itself (no second-level region; the batched path, pa_cap <= 64).
+bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassAMaxBlocks,
+               bool direct_partials = false) {
   if (n < 1 || m < n || s < n || n > kMaxN) return false;
   p->nmax = pick_nmax(n);
   p->NB = (p->nmax + 15) / 16;
   p->E = p->NB * (p->NB + 1) / 2 * 256;
   p->panels = (m + kWave - 1) / kWave;
   const int64_t blocks = (p->panels + kPassWaves - 1) / kPassWaves;
-  p->PA = (int)(blocks < kPassAMaxBlocks ? blocks : kPassAMaxBlocks);
+  p->PA = (int)(blocks < pa_cap ? blocks : pa_cap);
   const int64_t bblocks = ((m + 15) / 16 + kPassBThreads / kWave - 1) / (kPassBThreads / kWave);
   p->PB = (int)(bblocks < kPassBMaxBlocks ? bblocks : kPassBMaxBlocks);
-  p->G2 = (p->PA + kReduceChunk - 1) / kReduceChunk;  // <= kMaxPartial2 since PA <= 512
+  p->G2 = direct_partials ? p->PA : (p->PA + kReduceChunk - 1) / kReduceChunk;
   const int64_t rows = (s + 15) / 16;
   p->rpt = rows <= 4 ? 4 : rows <= 8 ? 8 : rows <= 12 ? 12 : rows <= 16 ? 16 : rows <= 24 ? 24 : 0;
   if (p->rpt == 0 && s > kMaxSketchRows) return false;
@@ -72,7 +79,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p) {
   p->off_part = off;
   off = align256(off + (size_t)p->PA * p->E * sizeof(double));
   p->off_part2 = off;
-  off = align256(off + (size_t)p->G2 * p->E * sizeof(double));
+  if (!direct_partials) off = align256(off + (size_t)p->G2 * p->E * sizeof(double));
   p->off_As = off;
   off = align256(off + (size_t)s * n * sizeof(double));
   p->total = off;
@@ -289,6 +296,296 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   return RPCHOLQR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched plans.
+
+constexpr int64_t kBatchPartialsMax = 64;   // pass-A workgroups (Gram partials) per problem
+constexpr int64_t kBatchPgroupsPerWG = 8;   // target panel groups per pass-A workgroup
+constexpr int64_t kBatchBIters = 16;        // target 4-block iterations per pass-B workgroup
+
+struct SizeClass {
+  int key = 0;                       // RPT (sketch classes) or NMAX (pass classes)
+  size_t probs_off = 0, items_a_off = 0, items_b_off = 0;  // offsets into the device buffer
+  int nprobs = 0;
+  int64_t items_a = 0, items_b = 0;
+  int64_t max_s = 0;
+};
+
+int32_t check_problem(int64_t m, int64_t n, int64_t s, const double* A, int64_t lda, const double* Q,
+                      int64_t ldq, const double* R, int64_t ldr) {
+  if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
+  if (!A || !Q || !R) return RPCHOLQR_EINVAL;
+  if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
+  const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
+  if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
+    return RPCHOLQR_EINVAL;
+  return RPCHOLQR_OK;
+}
+
+}  // namespace
+
+struct rpcholqr_batched_plan {
+  int64_t batch = 0;
+  void* dmem = nullptr;
+  size_t dbytes = 0;
+  size_t sk_off = 0, pa_off = 0, ch_off = 0, pb_off = 0, gather_off = 0;
+  int64_t gather_items = 0;
+  std::vector<SizeClass> sketch_classes, pass_classes;
+};
+
+namespace {
+
+template <typename T>
+T* at(const rpcholqr_batched_plan* p, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(p->dmem) + off);
+}
+
+int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s, const uint64_t* seed,
+                       const double* const* A, const int64_t* lda, double* const* Q, const int64_t* ldq,
+                       double* const* R, const int64_t* ldr, int32_t precision, rpcholqr_batched_plan** out,
+                       int64_t* bad_problem) {
+  if (bad_problem) *bad_problem = -1;
+  if (!out) return RPCHOLQR_EINVAL;
+  *out = nullptr;
+  if (batch < 1 || batch > INT32_MAX || !m || !n || !s || !seed || !A || !lda || !Q || !ldq || !R || !ldr)
+    return RPCHOLQR_EINVAL;
+  if (precision != RPCHOLQR_FP64) return RPCHOLQR_EUNSUPPORTED;
+  std::vector<Plan> plans((size_t)batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    int32_t rc = check_problem(m[b], n[b], s[b], A[b], lda[b], Q[b], ldq[b], R[b], ldr[b]);
+    if (rc == RPCHOLQR_OK) {
+      const int64_t panels = (m[b] + kWave - 1) / kWave;
+      const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+      int64_t pa = (pgroups + kBatchPgroupsPerWG - 1) / kBatchPgroupsPerWG;
+      pa = std::min<int64_t>(std::max<int64_t>(pa, 1), kBatchPartialsMax);
+      if (!make_plan(m[b], n[b], s[b], &plans[b], pa, true)) rc = RPCHOLQR_EUNSUPPORTED;
+    }
+    if (rc != RPCHOLQR_OK) {
+      if (bad_problem) *bad_problem = b;
+      return rc;
+    }
+  }
+  auto* p = new rpcholqr_batched_plan();
+  p->batch = batch;
+  // Size classes; problems within a class in decreasing m (largest work first).
+  std::vector<int64_t> order((size_t)batch);
+  for (int64_t b = 0; b < batch; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return m[x] > m[y]; });
+  std::map<int, std::vector<int32_t>> by_rpt, by_nmax;
+  for (int64_t b : order) {
+    by_rpt[plans[b].rpt].push_back((int32_t)b);
+    by_nmax[plans[b].nmax].push_back((int32_t)b);
+  }
+  // Host images of the device tables.
+  std::vector<SketchArgs> sk((size_t)batch);
+  std::vector<PassAArgs> pa((size_t)batch);
+  std::vector<CholArgs> ch((size_t)batch);
+  std::vector<PassBArgs> pb((size_t)batch);
+  std::vector<BatchItem> gather, items_a, items_b;
+  std::vector<int32_t> probs;
+  // Device buffer layout: tables, item lists, then the per-problem workspaces.
+  size_t off = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  p->sk_off = reserve(sizeof(SketchArgs) * batch);
+  p->pa_off = reserve(sizeof(PassAArgs) * batch);
+  p->ch_off = reserve(sizeof(CholArgs) * batch);
+  p->pb_off = reserve(sizeof(PassBArgs) * batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    const int64_t nb = ((int64_t)s[b] * n[b] + kGatherThreads - 1) / kGatherThreads;
+    for (int64_t i = 0; i < nb; ++i) gather.push_back(BatchItem{(int32_t)b, (int32_t)i, (int32_t)nb});
+  }
+  p->gather_items = (int64_t)gather.size();
+  p->gather_off = reserve(sizeof(BatchItem) * gather.size());
+  for (auto& kv : by_rpt) {
+    SizeClass c;
+    c.key = kv.first;
+    c.nprobs = (int)kv.second.size();
+    c.probs_off = reserve(sizeof(int32_t) * kv.second.size());
+    for (int32_t b : kv.second) c.max_s = std::max<int64_t>(c.max_s, s[b]);
+    p->sketch_classes.push_back(c);
+  }
+  for (auto& kv : by_nmax) {
+    SizeClass c;
+    c.key = kv.first;
+    c.nprobs = (int)kv.second.size();
+    c.probs_off = reserve(sizeof(int32_t) * kv.second.size());
+    for (int32_t b : kv.second) {
+      c.items_a += plans[b].PA;
+      const int64_t blocks16 = (m[b] + 15) / 16;
+      const int64_t per_wg = (int64_t)(kPassBThreads / kWave) * kBatchBIters;
+      c.items_b += std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
+    }
+    c.items_a_off = reserve(sizeof(BatchItem) * c.items_a);
+    c.items_b_off = reserve(sizeof(BatchItem) * c.items_b);
+    p->pass_classes.push_back(c);
+  }
+  std::vector<size_t> ws_off((size_t)batch);
+  for (int64_t b = 0; b < batch; ++b) ws_off[b] = reserve(plans[b].total);
+  p->dbytes = off;
+  if (hipMalloc(&p->dmem, p->dbytes) != hipSuccess) {
+    delete p;
+    return RPCHOLQR_EHIP;
+  }
+  char* base = static_cast<char*>(p->dmem);
+  for (int64_t b = 0; b < batch; ++b) {
+    const Plan& pl = plans[b];
+    char* w = base + ws_off[b];
+    SketchArgs& sa = sk[b];
+    sa = SketchArgs{};
+    sa.m = m[b];
+    sa.n = (int32_t)n[b];
+    sa.s = (int32_t)s[b];
+    sa.seed = seed[b];
+    sa.scale = std::sqrt((double)m[b] / (double)s[b]);
+    sa.A = A[b];
+    sa.lda = lda[b];
+    sa.As = (double*)(w + pl.off_As);
+    sa.tri = (double*)(w + pl.off_tri);
+    sa.Rs = (double*)(w + pl.off_Rs);
+    sa.nmax = pl.nmax;
+    PassAArgs& a = pa[b];
+    a = PassAArgs{};
+    a.m = m[b];
+    a.n = (int32_t)n[b];
+    a.A = A[b];
+    a.lda = lda[b];
+    a.tri_s = (const double*)(w + pl.off_tri);
+    a.partials = (double*)(w + pl.off_part);
+    a.W = Q[b];
+    a.ldw = ldq[b];
+    CholArgs& c = ch[b];
+    c = CholArgs{};
+    c.partial2 = (const double*)(w + pl.off_part);
+    c.G2 = pl.PA;
+    c.E = pl.E;
+    c.NB = pl.NB;
+    c.n = (int32_t)n[b];
+    c.nmax = pl.nmax;
+    c.Rs = (const double*)(w + pl.off_Rs);
+    c.T2 = (double*)(w + pl.off_tri2);
+    c.R = R[b];
+    c.ldr = ldr[b];
+    PassBArgs& q = pb[b];
+    q = PassBArgs{};
+    q.m = m[b];
+    q.n = (int32_t)n[b];
+    q.T2 = (const double*)(w + pl.off_tri2);
+    q.Q = Q[b];
+    q.ldq = ldq[b];
+  }
+  bool ok = hipMemcpy(at<SketchArgs>(p, p->sk_off), sk.data(), sizeof(SketchArgs) * batch,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(at<PassAArgs>(p, p->pa_off), pa.data(), sizeof(PassAArgs) * batch,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(at<CholArgs>(p, p->ch_off), ch.data(), sizeof(CholArgs) * batch, hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(at<PassBArgs>(p, p->pb_off), pb.data(), sizeof(PassBArgs) * batch,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(at<BatchItem>(p, p->gather_off), gather.data(), sizeof(BatchItem) * gather.size(),
+                      hipMemcpyHostToDevice) == hipSuccess;
+  {
+    size_t i = 0;
+    for (auto& kv : by_rpt) {
+      ok = ok && hipMemcpy(at<int32_t>(p, p->sketch_classes[i].probs_off), kv.second.data(),
+                           sizeof(int32_t) * kv.second.size(), hipMemcpyHostToDevice) == hipSuccess;
+      ++i;
+    }
+    i = 0;
+    for (auto& kv : by_nmax) {
+      SizeClass& c = p->pass_classes[i++];
+      items_a.clear();
+      items_b.clear();
+      for (int32_t b : kv.second) {
+        const int32_t na = plans[b].PA;
+        for (int32_t k = 0; k < na; ++k) items_a.push_back(BatchItem{b, k, na});
+        const int64_t blocks16 = (m[b] + 15) / 16;
+        const int64_t per_wg = (int64_t)(kPassBThreads / kWave) * kBatchBIters;
+        const int32_t nb = (int32_t)std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
+        for (int32_t k = 0; k < nb; ++k) items_b.push_back(BatchItem{b, k, nb});
+      }
+      ok = ok &&
+           hipMemcpy(at<int32_t>(p, c.probs_off), kv.second.data(), sizeof(int32_t) * kv.second.size(),
+                     hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(at<BatchItem>(p, c.items_a_off), items_a.data(), sizeof(BatchItem) * items_a.size(),
+                     hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(at<BatchItem>(p, c.items_b_off), items_b.data(), sizeof(BatchItem) * items_b.size(),
+                     hipMemcpyHostToDevice) == hipSuccess;
+    }
+  }
+  if (!ok) {
+    (void)hipFree(p->dmem);
+    delete p;
+    return RPCHOLQR_EHIP;
+  }
+  *out = p;
+  return RPCHOLQR_OK;
+}
+
+int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, void* stream) {
+  if (!p || !info) return RPCHOLQR_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int32_t* inf = (int32_t*)info;
+  const SketchArgs* sk = at<SketchArgs>(p, p->sk_off);
+  const PassAArgs* pa = at<PassAArgs>(p, p->pa_off);
+  const CholArgs* ch = at<CholArgs>(p, p->ch_off);
+  const PassBArgs* pb = at<PassBArgs>(p, p->pb_off);
+  // Lines 2-3 of Algorithm rpCholesky-QR for every problem.
+  hipLaunchKernelGGL(kb_gather, dim3((unsigned)p->gather_items), dim3(kGatherThreads), 0, st, sk,
+                     at<BatchItem>(p, p->gather_off));
+  for (const SizeClass& c : p->sketch_classes) {
+    const int32_t* probs = at<int32_t>(p, c.probs_off);
+    const dim3 g((unsigned)c.nprobs), blk(kSketchThreads);
+    switch (c.key) {
+      case 4: hipLaunchKernelGGL((kb_sketch_qr<4>), g, blk, 0, st, sk, probs, inf); break;
+      case 8: hipLaunchKernelGGL((kb_sketch_qr<8>), g, blk, 0, st, sk, probs, inf); break;
+      case 12: hipLaunchKernelGGL((kb_sketch_qr<12>), g, blk, 0, st, sk, probs, inf); break;
+      case 16: hipLaunchKernelGGL((kb_sketch_qr<16>), g, blk, 0, st, sk, probs, inf); break;
+      case 24: hipLaunchKernelGGL((kb_sketch_qr<24>), g, blk, 0, st, sk, probs, inf); break;
+      default:
+        hipLaunchKernelGGL(kb_sketch_qr_generic, g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs, inf);
+        break;
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  // Lines 4-8 of Algorithm Preconditioned Cholesky-QR, one launch per column class.
+  for (const SizeClass& c : p->pass_classes) {
+    const BatchItem* it = at<BatchItem>(p, c.items_a_off);
+    const dim3 g((unsigned)c.items_a), blk(kPassThreads);
+    switch (c.key) {
+      case 16: hipLaunchKernelGGL((kb_passA<16>), g, blk, 0, st, pa, it, inf); break;
+      case 32: hipLaunchKernelGGL((kb_passA<32>), g, blk, 0, st, pa, it, inf); break;
+      case 48: hipLaunchKernelGGL((kb_passA<48>), g, blk, 0, st, pa, it, inf); break;
+      default: hipLaunchKernelGGL((kb_passA<64>), g, blk, 0, st, pa, it, inf); break;
+    }
+  }
+  for (const SizeClass& c : p->pass_classes) {
+    const int32_t* probs = at<int32_t>(p, c.probs_off);
+    const dim3 g((unsigned)c.nprobs), blk(kCholThreads);
+    switch (c.key) {
+      case 16: hipLaunchKernelGGL((kb_cholesky<16>), g, blk, 0, st, ch, probs, inf); break;
+      case 32: hipLaunchKernelGGL((kb_cholesky<32>), g, blk, 0, st, ch, probs, inf); break;
+      case 48: hipLaunchKernelGGL((kb_cholesky<48>), g, blk, 0, st, ch, probs, inf); break;
+      default: hipLaunchKernelGGL((kb_cholesky<64>), g, blk, 0, st, ch, probs, inf); break;
+    }
+  }
+  for (const SizeClass& c : p->pass_classes) {
+    const BatchItem* it = at<BatchItem>(p, c.items_b_off);
+    const dim3 g((unsigned)c.items_b), blk(kPassBThreads);
+    switch (c.key) {
+      case 16: hipLaunchKernelGGL((kb_passB<16>), g, blk, 0, st, pb, it, inf); break;
+      case 32: hipLaunchKernelGGL((kb_passB<32>), g, blk, 0, st, pb, it, inf); break;
+      case 48: hipLaunchKernelGGL((kb_passB<48>), g, blk, 0, st, pb, it, inf); break;
+      default: hipLaunchKernelGGL((kb_passB<64>), g, blk, 0, st, pb, it, inf); break;
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  return RPCHOLQR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -339,6 +636,39 @@ int32_t rpcholqr_timing_read(double* ms, int32_t count) {
   }
   g_timing.used = 0;
   return (int32_t)calls;
+}
+
+int32_t rpcholqr_batched_plan_create(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,
+                                     const uint64_t* seed, const double* const* A, const int64_t* lda,
+                                     double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,
+                                     int32_t precision, rpcholqr_batched_plan** plan, int64_t* bad_problem) {
+  return batched_create(batch, m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, plan, bad_problem);
+}
+
+int32_t rpcholqr_batched_execute(const rpcholqr_batched_plan* plan, rpcholqr_info* info, void* stream) {
+  return batched_execute(plan, info, stream);
+}
+
+size_t rpcholqr_batched_plan_device_bytes(const rpcholqr_batched_plan* plan) { return plan ? plan->dbytes : 0; }
+
+int32_t rpcholqr_batched_plan_destroy(rpcholqr_batched_plan* plan) {
+  if (!plan) return RPCHOLQR_OK;
+  const bool ok = plan->dmem == nullptr || hipFree(plan->dmem) == hipSuccess;
+  delete plan;
+  return ok ? RPCHOLQR_OK : RPCHOLQR_EHIP;
+}
+
+int32_t rpcholqr_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,
+                                const uint64_t* seed, const double* const* A, const int64_t* lda,
+                                double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,
+                                int32_t precision, rpcholqr_info* info, void* stream, int64_t* bad_problem) {
+  rpcholqr_batched_plan* plan = nullptr;
+  int32_t rc = batched_create(batch, m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, &plan, bad_problem);
+  if (rc != RPCHOLQR_OK) return rc;
+  rc = batched_execute(plan, info, stream);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == RPCHOLQR_OK) rc = RPCHOLQR_EHIP;
+  const int32_t rc2 = rpcholqr_batched_plan_destroy(plan);
+  return rc != RPCHOLQR_OK ? rc : rc2;
 }
 
 }  // extern "C"

@@ -59,8 +59,8 @@ struct SketchArgs {
 };
 
 // Line 2: one thread per sample entry.
-__global__ __launch_bounds__(kGatherThreads) void k_gather(SketchArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * kGatherThreads + threadIdx.x;
+__device__ __forceinline__ void gather_body(const SketchArgs& a, int64_t bid) {
+  const int64_t e = bid * kGatherThreads + threadIdx.x;
   const int64_t total = (int64_t)a.s * a.n;
   if (e >= total) return;
   const int r = (int)(e % a.s), j = (int)(e / a.s);
@@ -70,6 +70,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(SketchArgs a) {
   if (a.As_out) a.As_out[e] = v;
   if (a.idx_out && j == 0) a.idx_out[r] = ir;
 }
+
+__global__ __launch_bounds__(kGatherThreads) void k_gather(SketchArgs a) { gather_body(a, blockIdx.x); }
 
 // XOR butterfly over the 16 lanes of a row (all lanes active):
 // h = 1, 2 by quad permutation, h = 4 by half-row mirror, h = 8 by row mirror.
@@ -127,7 +129,7 @@ __device__ __forceinline__ void sketch_status(const SketchArgs& a, int bad_k) {
 // k to its four columns, and the wave owning column k+1 then forms reflector
 // k+1 from the freshly updated column into the other LDS buffer.
 template <int RPT>
-__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
+__device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
   __shared__ double vbuf[2][16 * RPT];
   __shared__ double tau_s[2];
   __shared__ double Rl[kSketchMaxN * kSketchLdr];
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
 // Line 3 for large s: the same layout and operation order, with the sample
 // kept in global memory (a.As, worked on in place) and the Householder vector
 // in dynamic LDS (2 s doubles).  n <= 64.
-__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs a) {
+__device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
   extern __shared__ double vdyn[];  // [2][s]
   __shared__ double tau_s[2];
   __shared__ double Rl[kSketchMaxN * kSketchLdr];
@@ -303,5 +305,12 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs
   if (bad_k >= 0) return;
   sketch_finish(a, Rl);
 }
+
+template <int RPT>
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
+  sketch_qr_body<RPT>(a);
+}
+
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs a) { sketch_qr_generic_body(a); }
 
 }  // namespace rpq

@@ -95,7 +95,7 @@ __device__ __forceinline__ void store_d(double* M, int r0, int c0, int lane, d4 
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
+__device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   constexpr int NB = NMAX / 16;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int E = NT * 256;
@@ -113,13 +113,28 @@ __global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
   // every load first, then the sums in ascending partial index.  Zero the
   // lower triangles so that diagonal-block products see triangular operands.
   {
-    double v[PER][kMaxPartial2];
+    // Partials are summed in ascending index; they are loaded kMaxPartial2 at a
+    // time (every load of a round in flight together).
+    double acc[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * kCholThreads;
+    for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+    for (int g0 = 0; g0 < a.G2; g0 += kMaxPartial2) {
+      double v[PER][kMaxPartial2];
 #pragma unroll
-      for (int g = 0; g < kMaxPartial2; ++g)
-        v[u][g] = (e < E && g < a.G2) ? a.partial2[(int64_t)g * E + e] : 0.0;
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * kCholThreads;
+#pragma unroll
+        for (int g = 0; g < kMaxPartial2; ++g)
+          v[u][g] = (e < E && g0 + g < a.G2) ? a.partial2[(int64_t)(g0 + g) * E + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        double t = (g0 == 0) ? v[u][0] : acc[u] + v[u][0];
+#pragma unroll
+        for (int g = 1; g < kMaxPartial2; ++g)
+          if (g0 + g < a.G2) t = t + v[u][g];
+        acc[u] = t;
+      }
     }
     for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
       const int i = e / NMAX, j = e % NMAX;
@@ -141,11 +156,7 @@ __global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
           }
         const int bj = bi + rem;
         const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
-        double acc = v[u][0];
-#pragma unroll
-        for (int g = 1; g < kMaxPartial2; ++g)
-          if (g < a.G2) acc = acc + v[u][g];
-        if (i <= j) Gs[i * kCLd + j] = (j < n) ? acc : (i == j ? 1.0 : 0.0);
+        if (i <= j) Gs[i * kCLd + j] = (j < n) ? acc[u] : (i == j ? 1.0 : 0.0);
       }
     }
   }
@@ -291,6 +302,11 @@ __global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
       if (i / 16 > j / 16) a.R[i + (int64_t)j * a.ldr] = 0.0;
     }
   }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads, 1) void k_cholesky(CholArgs a) {
+  cholesky_body<NMAX>(a);
 }
 
 }  // namespace rpq

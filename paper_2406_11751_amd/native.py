@@ -27,6 +27,13 @@ SIGNATURES = {
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rpcholqr_timing_enable": (_i32, [_i32]),
     "rpcholqr_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), _i32]),
+    "rpcholqr_batched_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_i64)]),
+    "rpcholqr_batched_execute": (_i32, [_vp, _vp, _vp]),
+    "rpcholqr_batched_plan_device_bytes": (_sz, [_vp]),
+    "rpcholqr_batched_plan_destroy": (_i32, [_vp]),
+    "rpcholqr_factor_batched": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                       ctypes.POINTER(_i64)]),
 }
 NSTAGES = 5
 STAGES = ("sketch", "passA", "reduce", "cholesky", "passB")
@@ -152,3 +159,95 @@ def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, s
             raise RpCholQRError(f"numerical failure {INFO.get(code, code)} at column {index}", code=code,
                                 index=index)
     return (Q, R, info, extra) if debug else (Q, R, info)
+
+
+class BatchedPlan:
+    """A batch of independent factorizations planned once and executed any
+    number of times (rpcholqr_batched_plan_*).  The plan keeps references to the
+    caller's A, Q and R tensors; Q and R are allocated here when not given."""
+
+    def __init__(self, As, s, seeds, *, Qs=None, Rs=None, precision: int = FP64):
+        import torch
+
+        lib = load_library()
+        b = len(As)
+        if b < 1:
+            raise ValueError("empty batch")
+        s = list(s) if hasattr(s, "__len__") else [s] * b
+        seeds = list(seeds) if hasattr(seeds, "__len__") else [seeds + i for i in range(b)]
+        if Qs is None:
+            Qs = [colmajor_empty(A.shape[0], A.shape[1], A.device) for A in As]
+        if Rs is None:
+            Rs = [colmajor_empty(A.shape[1], A.shape[1], A.device) for A in As]
+        self.As, self.Qs, self.Rs = list(As), list(Qs), list(Rs)
+        self.batch = b
+        self.device = As[0].device
+        I64 = ctypes.c_int64 * b
+        P = ctypes.c_void_p * b
+        m = I64(*[A.shape[0] for A in As])
+        n = I64(*[A.shape[1] for A in As])
+        sv = I64(*s)
+        sd = (ctypes.c_uint64 * b)(*[int(x) & (2**64 - 1) for x in seeds])
+        lda = I64(*[_ld(A, A.shape[0]) for A in As])
+        ldq = I64(*[_ld(Q, A.shape[0]) for Q, A in zip(Qs, As)])
+        ldr = I64(*[_ld(R, A.shape[1]) for R, A in zip(Rs, As)])
+        pa = P(*[A.data_ptr() for A in As])
+        pq = P(*[Q.data_ptr() for Q in Qs])
+        pr = P(*[R.data_ptr() for R in Rs])
+        handle = ctypes.c_void_p()
+        bad = ctypes.c_int64(-1)
+        with torch.cuda.device(self.device):
+            rc = lib.rpcholqr_batched_plan_create(b, m, n, sv, sd, pa, lda, pq, ldq, pr, ldr, precision,
+                                                  ctypes.byref(handle), ctypes.byref(bad))
+        if rc != 0:
+            raise RpCholQRError(f"rpcholqr_batched_plan_create returned {STATUS.get(rc, rc)} "
+                                f"(problem {bad.value})", status=rc)
+        self._h = handle
+        self.device_bytes = int(lib.rpcholqr_batched_plan_device_bytes(handle))
+
+    def execute(self, info=None, stream=None, check: bool = True):
+        """Launches the batch; returns the (batch, 2) int32 device info tensor.
+        With check=True the stream is synchronized and any failed problem raises."""
+        import torch
+
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        if info is None:
+            info = torch.empty((self.batch, 2), dtype=torch.int32, device=self.device)
+        st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream)
+        rc = load_library().rpcholqr_batched_execute(self._h, _ptr(info), st)
+        if rc != 0:
+            raise RpCholQRError(f"rpcholqr_batched_execute returned {STATUS.get(rc, rc)}", status=rc)
+        if check:
+            torch.cuda.synchronize(self.device)
+            bad = (info[:, 0] != 0).nonzero()
+            if bad.numel():
+                i = int(bad[0, 0])
+                code, index = (int(v) for v in info[i].tolist())
+                raise RpCholQRError(f"problem {i}: numerical failure {INFO.get(code, code)} at column {index}",
+                                    code=code, index=index)
+        return info
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            import torch
+
+            torch.cuda.synchronize(self.device)
+            load_library().rpcholqr_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factor_batched(As, s, seeds, *, check: bool = True, precision: int = FP64):
+    """Thin QR of every matrix in As.  Returns (Qs, Rs, info)."""
+    plan = BatchedPlan(As, s, seeds, precision=precision)
+    try:
+        info = plan.execute(check=check)
+    finally:
+        plan.close()
+    return plan.Qs, plan.Rs, info
