@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="bounded CPU sample: repeat oracle factorizations for about this long")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (for counter calibration)")
     return ap.parse_args()
@@ -65,6 +67,63 @@ def measured_traffic(pass_name: str, m: int, n: int):
     if rec.get("source_digest") != profiling.source_digest():
         return None
     return rec["traffic_bytes"]
+
+
+def batched_measurement(args, torch, rq, gen_usv, metrics):
+    """Batched workload: the 2048-problem list (m ~ U{2000..200000}, n ~ U{8, 16,
+    32, 64, 128}, log10 kappa ~ U[2, 14], s = 3n, seed i) without its n = 128
+    problems (beyond this build's largest n), generated on the GPU.  Times whole
+    executions of one batched plan and, for comparison, the same problems
+    factored one call at a time with the single-problem entry point."""
+    from workloads import batched_problem_list
+
+    dev = torch.device("cuda:0")
+    plist = batched_problem_list(2048, 0)
+    keep = [p for p in plist if p["n"] <= rq.max_n()]
+    t0 = time.time()
+    As = []
+    for i, p in enumerate(keep):
+        As.append(gen_usv(p["m"], p["n"], p["kappa"], p["seed"], backend="torch", device=dev))
+        if (i + 1) % 256 == 0:
+            print(f"# batched inputs: {i + 1}/{len(keep)} ({time.time() - t0:.0f}s)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    print(f"# batched inputs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    plan = rq.BatchedPlan(As, [p["s"] for p in keep], [p["seed"] for p in keep])
+    info = torch.zeros((len(keep), 2), dtype=torch.int32, device=dev)
+    plan.execute(info=info)  # warm-up and check
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.batched_steps):
+        plan.execute(info=info, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batched_steps
+    assert int((info[:, 0] != 0).sum()) == 0
+    orth = max(metrics.orth_error(plan.Qs[i]) for i in range(0, len(keep), 64))
+    # the same problems one call at a time (single-problem entry point, its own workspace each)
+    ws = torch.empty(max(rq.workspace_bytes(p["m"], p["n"], p["s"]) for p in keep), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for A, Q, R, p in zip(As, plan.Qs, plan.Rs, keep):
+        rq.factor(A, p["s"], p["seed"], Q=Q, R=R, workspace=ws, info=info[0], check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    bytes_alg = sum(24.0 * p["m"] * p["n"] for p in keep)
+    out = dict(workload="2048-problem list (m ~ U{2000..200000}, n ~ U{8,16,32,64,128}, log10 kappa ~ U[2,14], "
+                        "s = 3n, seed i), n = 128 problems excluded",
+               problems=len(keep), excluded_n128=len(plist) - len(keep), ms_per_batch=ms,
+               factorizations_per_s=len(keep) / (ms * 1e-3), value_GBps=bytes_alg / (ms * 1e-3) / 1e9,
+               sequential_single_calls_ms=seq_ms, speedup_vs_single_calls=seq_ms / ms,
+               max_orth_every_64th=orth, device_bytes=plan.device_bytes)
+    plan.close()
+    del As
+    torch.cuda.empty_cache()
+    print(f"# batched: {len(keep)} problems in {ms:.2f} ms ({out['factorizations_per_s']:.0f} fact/s, "
+          f"{out['value_GBps']:.0f} GB/s); one call at a time {seq_ms:.1f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -191,6 +250,8 @@ def main():
                    sample=f"{runs} full oracle factorizations of the same {m}x{n} input, s={s} "
                           f"({runs * dt:.1f} s of CPU work)")
 
+    batched = None if args.no_batched else batched_measurement(args, torch, rq, gen_usv, metrics)
+
     out = {
         "metric": METRIC,
         "value": bytes_alg / (ms * 1e-3) / 1e9,
@@ -215,6 +276,7 @@ def main():
                                     model="sum over passes of max(bytes/8 TB/s, flops/78.6 TF)"),
         "accuracy": acc,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 
