@@ -53,8 +53,16 @@ typedef enum {
   RPCHOLQR_EUNSUPPORTED = -4 /* n or s beyond what this build supports (rpcholqr_max_n()) */
 } rpcholqr_status;
 
-/* Arithmetic of the passes over A.  Only RPCHOLQR_FP64 is available in this
- * version; the others return RPCHOLQR_EUNSUPPORTED. */
+/* Arithmetic of the passes over A.
+ *   RPCHOLQR_FP64          every step in binary64 (the paper's algorithm).
+ *   RPCHOLQR_FP32_REFINE   not in the paper: step 5's Gram matrix A1^T A1 is
+ *       formed in binary32 (A1 rounded to float, float products and sums); the
+ *       row solves of steps 4 and 7 stay binary64, so A = Q1 (R2 R_s) holds to
+ *       binary64 accuracy, and Q1's loss of orthogonality (about u32 kappa(A1)^2)
+ *       is removed by a second, binary64 Cholesky-QR pass on Q1 (Cholesky-QR2,
+ *       Section 1): G = Q1^T Q1 = R3^T R3, Q = Q1 R3^{-1}, R = R3 (R2 R_s).
+ *       Needs a larger workspace (rpcholqr_workspace_bytes with this value).
+ *   RPCHOLQR_BF16X2_REFINE reserved; returns RPCHOLQR_EUNSUPPORTED. */
 typedef enum {
   RPCHOLQR_FP64 = 0,
   RPCHOLQR_FP32_REFINE = 1,
@@ -73,6 +81,8 @@ typedef struct {
 /* Cholesky of G1 (step 6): a pivot is not positive or not finite (the
  * hypothesis kappa(A1)^2 gamma_2 < 1 of Theorem t_perturb2 failed). */
 #define RPCHOLQR_INFO_ECHOL 2
+/* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
+#define RPCHOLQR_INFO_ECHOL2 3
 
 /* Largest n this build accepts. */
 int32_t rpcholqr_max_n(void);
@@ -116,7 +126,8 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
  * factor call records an event on its stream before the first kernel and after
  * each of its NSTAGES kernels (in order: sketch = sample + gather + sketch QR,
  * pass A = A1 and Gram partials, reduce = partial Gram sum, cholesky =
- * Cholesky, R2^{-1} and R product, pass B = Q = A1 R2^{-1} in place).  No device memory is
+ * Cholesky, R2^{-1} and R product, pass B = Q = A1 R2^{-1} in place; with a
+ * refined precision the last stage also holds the whole second pass).  No device memory is
  * allocated.  Process-wide state: do not time calls from several host threads
  * at once.
  *   rpcholqr_timing_enable(1) starts recording (and discards earlier records),

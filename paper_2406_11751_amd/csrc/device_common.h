@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rpq {
 
 constexpr int kWave = 64;
@@ -14,6 +16,7 @@ constexpr int kWaitLgkm0 = 0xC07F;  // lgkmcnt(0) only
 constexpr int kWaitVm0 = 0x0F70;    // vmcnt(0) only
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter form: output number
 // r of the generator seeded with `seed` is mix64(seed + (r+1)*golden_gamma).

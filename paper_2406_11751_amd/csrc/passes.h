@@ -88,22 +88,31 @@ __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[N
 }
 
 // pass A (NMAX a multiple of 16, <= 64).
-// LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 doubles.
-template <int NMAX>
+// MODE kSolveGram: A1 = A R_s^{-1} (stored in W) and its Gram partial.
+// MODE kGramOnly:  the Gram partial of A itself (used for Q1 in the second
+//                  Cholesky-QR pass of the refined precisions).
+// GP: arithmetic of the Gram contraction, FP64 (v_mfma_f64_16x16x4f64) or FP32
+//     (A1 rounded to float, v_mfma_f32_16x16x4f32, FP32 accumulation).
+// LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 elements.
+constexpr int kSolveGram = 0, kGramOnly = 1;
+constexpr int kGramF64 = 0, kGramF32 = 1;
+
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
 __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk) {
   static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA Gram tiles");
   constexpr int NB = GramShape<NMAX>::NB, NT = GramShape<NMAX>::NT, E = GramShape<NMAX>::E;
   constexpr int LDX = NMAX + 1;
   constexpr int XS = 32 * LDX;  // doubles per wave
   constexpr int LDS_D = (kPassWaves * XS > kPassWaves * E) ? kPassWaves * XS : kPassWaves * E;
+  using Acc = std::conditional_t<GP == kGramF64, d4, f4>;
   __shared__ double lds[LDS_D];
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   double* xs = lds + wave * XS;
   const int64_t panels = (a.m + kWave - 1) / kWave;
-  d4 acc[NT];
+  Acc acc[NT];
 #pragma unroll
-  for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < NT; ++q) acc[q] = Acc{0, 0, 0, 0};
   const int half_row = lane & 31;
   const int rq = lane >> 4, cq = lane & 15;  // MFMA operand position
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
@@ -113,53 +122,80 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
     double t[NMAX];
     load_row<NMAX>(t, a.A, r0, a.lda, a.n, lane, valid);
     pin_values(t);
-    trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
-    pin_values(t);
-    if (!valid) {
+    if constexpr (MODE == kSolveGram) {
+      trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
+      pin_values(t);
+      if (!valid) {
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
+        for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
+      }
+      store_a1<NMAX>(a, t, r0, lane, valid);
     }
-    store_a1<NMAX>(a, t, r0, lane, valid);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      wave_lds_fence();
-      if ((lane >> 5) == h) {
+      if constexpr (GP == kGramF64) {
+        wave_lds_fence();
+        if ((lane >> 5) == h) {
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j) xs[half_row * LDX + j] = t[j];
-      }
-      wave_lds_fence();
+          for (int j = 0; j < NMAX; ++j) xs[half_row * LDX + j] = t[j];
+        }
+        wave_lds_fence();
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {  // 4-row chunks of the half panel
-        double v[NB];
+        for (int q = 0; q < 8; ++q) {  // 4-row chunks of the half panel
+          double v[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) v[b] = xs[(4 * q + rq) * LDX + 16 * b + cq];
-        int tt = 0;
+          for (int b = 0; b < NB; ++b) v[b] = xs[(4 * q + rq) * LDX + 16 * b + cq];
+          int tt = 0;
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
+          for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-          for (int bj = bi; bj < NB; ++bj) {
-            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[tt], 0, 0, 0);
-            ++tt;
-          }
+            for (int bj = bi; bj < NB; ++bj) {
+              acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[tt], 0, 0, 0);
+              ++tt;
+            }
+        }
+      } else {
+        float* xf = reinterpret_cast<float*>(xs);
+        wave_lds_fence();
+        if ((lane >> 5) == h) {
+#pragma unroll
+          for (int j = 0; j < NMAX; ++j) xf[half_row * LDX + j] = (float)t[j];
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float v[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) v[b] = xf[(4 * q + rq) * LDX + 16 * b + cq];
+          int tt = 0;
+#pragma unroll
+          for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj) {
+              acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[bi], v[bj], acc[tt], 0, 0, 0);
+              ++tt;
+            }
+        }
       }
     }
   }
   __syncthreads();
-  // D(i, j) of a 16x16 f64 MFMA tile sits in lane j + 16*(i%4), register i/4.
+  // Result element (i, j) of a 16x16 tile sits in lane j + 16 (i mod 4), register
+  // i / 4 for the FP64 MFMA, and in lane j + 16 (i / 4), register i mod 4 for FP32.
 #pragma unroll
   for (int q = 0; q < NT; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = (lane >> 4) + 4 * v, j = lane & 15;
-      lds[wave * E + q * 256 + i * 16 + j] = acc[q][v];
+      const int i = (GP == kGramF64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v, j = lane & 15;
+      lds[wave * E + q * 256 + i * 16 + j] = (double)acc[q][v];
     }
   __syncthreads();
   sum_waves_to_partial<E>(lds, a.partials, bid);
 }
 
-template <int NMAX>
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
 __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
-  passA_body<NMAX>(a, blockIdx.x, gridDim.x);
+  passA_body<NMAX, MODE, GP>(a, blockIdx.x, gridDim.x);
 }
 
 // pass A, LDS-staged ping-pong (NMAX a multiple of 16, <= 64; columns 16-byte

@@ -8,6 +8,7 @@
 #include <array>
 #include <atomic>
 #include <map>
+#include <type_traits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -37,7 +38,7 @@ struct Plan {
   int64_t panels = 0;
   int PA = 0, PB = 0, G2 = 0;
   int rpt = 0;  // sample rows per lane in the register sketch QR; 0 = generic kernel
-  size_t off_tri = 0, off_tri2 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0;
+  size_t off_tri = 0, off_tri2 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0, off_R1 = 0;
   size_t total = 0;
 };
 
@@ -54,7 +55,7 @@ int pick_nmax(int64_t n) {
 // workgroups (= Gram partials).  With direct_partials the Cholesky kernel sums
 // the partials itself (no second-level region; the batched path, pa_cap <= 64).
 bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassAMaxBlocks,
-               bool direct_partials = false) {
+               bool direct_partials = false, bool refine = false) {
   if (n < 1 || m < n || s < n || n > kMaxN) return false;
   p->nmax = pick_nmax(n);
   p->NB = (p->nmax + 15) / 16;
@@ -82,6 +83,8 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
   if (!direct_partials) off = align256(off + (size_t)p->G2 * p->E * sizeof(double));
   p->off_As = off;
   off = align256(off + (size_t)s * n * sizeof(double));
+  p->off_R1 = off;  // refined precisions: R2 R_s of the first pass, n x n, ld n
+  if (refine) off = align256(off + (size_t)n * n * sizeof(double));
   p->total = off;
   return true;
 }
@@ -127,19 +130,21 @@ int device_cus() {
 // Pass A launch: the LDS-staged kernel when columns are 16-byte aligned, with
 // one wave of work per SIMD slot the LDS allows; else the register kernel.
 // Returns the number of workgroups launched (= Gram partials written), 0 on error.
-template <int NMAX>
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
 int launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
-  const bool aligned = ((uintptr_t)a.A % 16 == 0) && (a.lda % 2 == 0);
-  const int cus = kStagedPassA ? device_cus() : 0;
-  if (kStagedPassA && aligned && cus > 0) {
-    const int64_t pgroups = (p.panels + kPPWaves - 1) / kPPWaves;
-    const int64_t slots = (int64_t)cus * PassAPP<NMAX>::OCC;
-    int64_t grid = pgroups < slots ? pgroups : slots;
-    if (grid > p.PA) grid = p.PA;
-    hipLaunchKernelGGL((k_passA_pp<NMAX>), dim3((unsigned)grid), dim3(kPPThreads), 0, st, a);
-    return (int)grid;
+  if constexpr (MODE == kSolveGram && GP == kGramF64) {
+    const bool aligned = ((uintptr_t)a.A % 16 == 0) && (a.lda % 2 == 0);
+    const int cus = kStagedPassA ? device_cus() : 0;
+    if (kStagedPassA && aligned && cus > 0) {
+      const int64_t pgroups = (p.panels + kPPWaves - 1) / kPPWaves;
+      const int64_t slots = (int64_t)cus * PassAPP<NMAX>::OCC;
+      int64_t grid = pgroups < slots ? pgroups : slots;
+      if (grid > p.PA) grid = p.PA;
+      hipLaunchKernelGGL((k_passA_pp<NMAX>), dim3((unsigned)grid), dim3(kPPThreads), 0, st, a);
+      return (int)grid;
+    }
   }
-  hipLaunchKernelGGL((k_passA_mfma<NMAX>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL((k_passA_mfma<NMAX, MODE, GP>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
   return p.PA;
 }
 
@@ -167,6 +172,17 @@ hipEvent_t* timing_slot() {
   return g_timing.sets[g_timing.used++].data();
 }
 
+// Calls fn(std::integral_constant<int, NMAX>) for the plan's NMAX.
+template <typename F>
+void with_nmax(int nmax, F&& fn) {
+  switch (nmax) {
+    case 16: fn(std::integral_constant<int, 16>{}); break;
+    case 32: fn(std::integral_constant<int, 32>{}); break;
+    case 48: fn(std::integral_constant<int, 48>{}); break;
+    default: fn(std::integral_constant<int, 64>{}); break;
+  }
+}
+
 int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
                     double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision, void* ws,
                     size_t ws_bytes, rpcholqr_info* info, void* stream, int64_t* idx, double* As,
@@ -174,9 +190,10 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
   if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
-  if (precision != RPCHOLQR_FP64) return RPCHOLQR_EUNSUPPORTED;
+  const bool refine = precision == RPCHOLQR_FP32_REFINE;
+  if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
   Plan p;
-  if (!make_plan(m, n, s, &p)) return RPCHOLQR_EUNSUPPORTED;
+  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, refine)) return RPCHOLQR_EUNSUPPORTED;
   const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
   if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
     return RPCHOLQR_EINVAL;
@@ -191,6 +208,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   double* Rs_ws = (double*)(base + p.off_Rs);
   double* part = (double*)(base + p.off_part);
   double* part2 = (double*)(base + p.off_part2);
+  double* R1 = (double*)(base + p.off_R1);
   int32_t* inf = (int32_t*)info;
   hipEvent_t* ev = timing_slot();
   int stage = 0;
@@ -223,7 +241,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
-  // Lines 4 (A1 = A R_s^{-1}) and 5 (Gram partials).
+  // Lines 4 (A1 = A R_s^{-1}, stored in Q) and 5 (Gram partials; FP32 when refining).
   PassAArgs pa;
   pa.m = m;
   pa.n = (int32_t)n;
@@ -235,12 +253,10 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pa.W = Q;
   pa.ldw = ldq;
   int pa_grid = 0;
-  switch (p.nmax) {
-    case 16: pa_grid = launch_passes_A<16>(p, pa, st); break;
-    case 32: pa_grid = launch_passes_A<32>(p, pa, st); break;
-    case 48: pa_grid = launch_passes_A<48>(p, pa, st); break;
-    default: pa_grid = launch_passes_A<64>(p, pa, st); break;
-  }
+  with_nmax(p.nmax, [&](auto nm) {
+    constexpr int NM = decltype(nm)::value;
+    pa_grid = refine ? launch_passes_A<NM, kSolveGram, kGramF32>(p, pa, st) : launch_passes_A<NM>(p, pa, st);
+  });
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   const int g2 = (pa_grid + kReduceChunk - 1) / kReduceChunk;  // <= p.G2
   mark();
@@ -253,7 +269,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
-  // Lines 5-6 (Cholesky) and 8 (R = R2 R_s).
+  // Lines 5-6 (Cholesky, R2^{-1}) and 8 (R = R2 R_s; into R1 when refining).
   CholArgs ca;
   ca.partial2 = part2;
   ca.G2 = g2;
@@ -263,21 +279,23 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   ca.nmax = p.nmax;
   ca.Rs = Rs_ws;
   ca.T2 = tri2;
-  ca.R = R;
-  ca.ldr = ldr;
+  ca.R = refine ? R1 : R;
+  ca.ldr = refine ? n : ldr;
   ca.info = inf;
   ca.G1_out = G1;
   ca.R2_out = R2;
-  switch (p.nmax) {
-    case 16: hipLaunchKernelGGL((k_cholesky<16>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
-    case 32: hipLaunchKernelGGL((k_cholesky<32>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
-    case 48: hipLaunchKernelGGL((k_cholesky<48>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
-    default: hipLaunchKernelGGL((k_cholesky<64>), dim3(1), dim3(kCholThreads), 0, st, ca); break;
-  }
+  ca.fail_code = RPCHOLQR_INFO_ECHOL;
+  auto cholesky = [&](const CholArgs& c) {
+    with_nmax(p.nmax, [&](auto nm) {
+      constexpr int NM = decltype(nm)::value;
+      hipLaunchKernelGGL((k_cholesky<NM>), dim3(1), dim3(kCholThreads), 0, st, c);
+    });
+  };
+  cholesky(ca);
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
-  // Line 6: Q = A1 R2^{-1}, A1 recomputed from A.
+  // Line 6: Q = A1 R2^{-1} in place over A1.
   PassBArgs pb;
   pb.m = m;
   pb.n = (int32_t)n;
@@ -285,13 +303,39 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pb.Q = Q;
   pb.ldq = ldq;
   pb.info = inf;
-  switch (p.nmax) {
-    case 16: launch_pass_B<16>(p, pb, st); break;
-    case 32: launch_pass_B<32>(p, pb, st); break;
-    case 48: launch_pass_B<48>(p, pb, st); break;
-    default: launch_pass_B<64>(p, pb, st); break;
-  }
+  auto pass_b = [&]() {
+    with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
+  };
+  pass_b();
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+
+  if (refine) {
+    // Second pass in FP64 (Cholesky-QR on Q1 = A1 R2^{-1}): G = Q1^T Q1,
+    // G = R3^T R3, Q = Q1 R3^{-1} in place, R = R3 (R2 R_s).
+    PassAArgs pg = pa;
+    pg.A = Q;
+    pg.lda = ldq;
+    pg.tri_s = nullptr;
+    pg.W = nullptr;
+    int pg_grid = 0;
+    with_nmax(p.nmax, [&](auto nm) {
+      pg_grid = launch_passes_A<decltype(nm)::value, kGramOnly, kGramF64>(p, pg, st);
+    });
+    const int g2b = (pg_grid + kReduceChunk - 1) / kReduceChunk;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((p.E + kReduceThreads - 1) / kReduceThreads, g2b),
+                       dim3(kReduceThreads), 0, st, (const double*)part, pg_grid, p.E, part2, (const int32_t*)inf);
+    CholArgs c2 = ca;
+    c2.G2 = g2b;
+    c2.Rs = R1;
+    c2.R = R;
+    c2.ldr = ldr;
+    c2.G1_out = nullptr;
+    c2.R2_out = nullptr;
+    c2.fail_code = RPCHOLQR_INFO_ECHOL2;
+    cholesky(c2);
+    pass_b();
+    if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  }
   mark();
   return RPCHOLQR_OK;
 }
@@ -469,6 +513,7 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
     c.T2 = (double*)(w + pl.off_tri2);
     c.R = R[b];
     c.ldr = ldr[b];
+    c.fail_code = RPCHOLQR_INFO_ECHOL;
     PassBArgs& q = pb[b];
     q = PassBArgs{};
     q.m = m[b];
@@ -593,9 +638,9 @@ extern "C" {
 int32_t rpcholqr_max_n(void) { return kMaxN; }
 
 size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision) {
-  if (precision != RPCHOLQR_FP64) return 0;
+  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE) return 0;
   Plan p;
-  if (!make_plan(m, n, s, &p)) return 0;
+  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, precision == RPCHOLQR_FP32_REFINE)) return 0;
   return p.total;
 }
 

@@ -46,6 +46,7 @@ struct CholArgs {
   int32_t* info;
   double* G1_out;       // optional n x n, ld n (upper triangle)
   double* R2_out;       // optional n x n, ld n
+  int32_t fail_code;    // info code for a failed pivot (ECHOL, or ECHOL2 in a second pass)
 };
 
 // Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
@@ -215,7 +216,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
     __syncthreads();
     if (bad_s >= 0) {
       if (tid == 0) {
-        a.info[0] = 2;
+        a.info[0] = a.fail_code;
         a.info[1] = bad_s;
       }
       return;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "librpcholqr.so")
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "EWORKSPACE", -4: "EUNSUPPORTED"}
-INFO = {0: "OK", 1: "ESKETCH", 2: "ECHOL"}
+INFO = {0: "OK", 1: "ESKETCH", 2: "ECHOL", 3: "ECHOL2"}
 FP64, FP32_REFINE, BF16X2_REFINE = 0, 1, 2
 
 # Every function the header declares, with its ctypes signature.

@@ -1,0 +1,111 @@
+"""GPU parity of the refined precision RPCHOLQR_FP32_REFINE against the FP64 oracle.
+
+Pass 1 keeps the FP64 row solves, so the sampled indices, A_s, R_s and A1 are
+bit-identical to the oracle's; its Gram matrix is formed in FP32 and is checked
+against an FP32 emulation and against the FP64 Gram at the FP32 rounding
+level.  After the FP64 second pass, Q and R must agree with the FP64 oracle
+within 1e-12 relative Frobenius error, with orth <= 1e-12 and residual <= 1e-15.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen_usv, metrics
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = 1e-12
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def rq():
+    import paper_2406_11751_amd
+
+    return paper_2406_11751_amd
+
+
+def dev(A_h):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A_h).T)).to("cuda").t()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def announce(*args):
+    print("case:", *args, flush=True)
+
+
+CASES = [
+    (1, 1, 1, 1.0, 0), (37, 1, 3, 1.0, 1), (1000, 8, 24, 1e8, 3), (4099, 16, 48, 1e15, 5),
+    (6001, 32, 96, 1e10, 7), (2500, 48, 144, 1e14, 9), (10000, 50, 150, 1e8, 0), (7777, 64, 192, 1e15, 11),
+    (20000, 64, 520, 1e12, 14), (65, 33, 99, 1e2, 16),
+]
+
+
+def check_refine(A_h, s, seed):
+    m, n = A_h.shape
+    announce(f"FP32_REFINE m={m} n={n} s={s} seed={seed}")
+    Q, R, info, ex = rq().factor(dev(A_h), s, seed, precision=rq().FP32_REFINE, debug=True)
+    ref = oracle.rpcholqr(A_h, s, seed, nthreads=NTHREADS)
+    assert np.array_equal(host(ex["idx"]), ref.idx)
+    assert np.array_equal(host(ex["Rs"]), ref.Rs)
+    a1 = host(ex["A1"])
+    assert np.array_equal(a1, ref.A1), "A1 differs"
+    # pass-1 Gram: FP32 arithmetic on A1 rounded to float
+    g1 = np.triu(host(ex["G1"]))
+    a1f = a1.astype(np.float32)
+    g32 = np.triu((a1f.T @ a1f).astype(np.float64))
+    scale = max(1.0, float(np.abs(ref.G1).max()))
+    # both sums carry about sqrt(rows) float roundings of size 2^-24 relative to |G1|
+    assert np.abs(g1 - g32).max() / scale < 8 * np.sqrt(m) * 2.0**-24 + 1e-6
+    assert metrics.rel_fro(g1, np.triu(ref.G1)) < 1e-5
+    Qh, Rh = host(Q), host(R)
+    eq, er = metrics.rel_fro(Qh, ref.Q), metrics.rel_fro(Rh, ref.R)
+    orth, res = metrics.orth_error(Qh), metrics.residual(A_h, Qh, Rh)
+    print(f"  |dQ|={eq:.2e} |dR|={er:.2e} orth={orth:.2e} res={res:.2e} |dG1|={metrics.rel_fro(g1, np.triu(ref.G1)):.1e}",
+          flush=True)
+    assert eq < TOL and er < TOL
+    assert orth < (1e-12 if s >= 2 * n else 1e-10) and res < 1e-15
+    assert np.array_equal(np.tril(Rh, -1), np.zeros((n, n)))
+
+
+@pytest.mark.parametrize("m,n,s,kappa,seed", CASES)
+def test_fp32_refine_small(m, n, s, kappa, seed):
+    check_refine(gen_usv(m, n, kappa, 200 + seed), s, seed)
+
+
+def test_fp32_refine_full_size():
+    m, n, s = 1_000_000, 64, 192
+    A_h = gen_usv(m, n, 1e12, 0)
+    announce("FP32_REFINE 1e6 x 64")
+    A = dev(A_h)
+    Q, R, _ = rq().factor(A, s, 0, precision=rq().FP32_REFINE)
+    ref = oracle.rpcholqr(A_h, s, 0, nthreads=NTHREADS)
+    assert metrics.rel_fro(host(Q), ref.Q) < TOL and metrics.rel_fro(host(R), ref.R) < TOL
+    assert metrics.orth_error(Q) < 1e-12 and metrics.residual(A, Q, R) < 1e-15
+
+
+def test_refine_workspace_and_unsupported():
+    lib = rq().load_library()
+    assert rq().workspace_bytes(10000, 50, 150, rq().FP32_REFINE) > rq().workspace_bytes(10000, 50, 150)
+    assert rq().workspace_bytes(10000, 50, 150, rq().BF16X2_REFINE) == 0
+    A = dev(gen_usv(1000, 8, 10.0, 1))
+    with pytest.raises(rq().RpCholQRError):
+        rq().factor(A, 24, 0, precision=rq().BF16X2_REFINE)
+    # a workspace sized for FP64 is too small for the refined precision
+    ws = torch.empty(rq().workspace_bytes(1000, 8, 24), dtype=torch.uint8, device="cuda")
+    Q = rq().colmajor_empty(1000, 8, "cuda")
+    R = rq().colmajor_empty(8, 8, "cuda")
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    import ctypes
+    P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    need = rq().workspace_bytes(1000, 8, 24, rq().FP32_REFINE)
+    if need > ws.numel():
+        rc = lib.rpcholqr_factor(1000, 8, 24, 0, P(A), 1000, P(Q), 1000, P(R), 8, rq().FP32_REFINE, P(ws),
+                                 ws.numel(), P(info), None)
+        assert rc == -3
