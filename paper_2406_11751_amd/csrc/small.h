@@ -137,9 +137,22 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
         acc[u] = t;
       }
     }
-    for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
-      const int i = e / NMAX, j = e % NMAX;
-      Rsl[i * kCLd + j] = (i <= j && j < n) ? a.Rs[i + j * n] : 0.0;
+    // R_s is column-major: consecutive threads take consecutive rows i of a
+    // column.  The loads are unconditional (clamped in bounds) so that all of
+    // them are in flight together; the selection happens afterwards.
+    constexpr int U = NMAX * NMAX / kCholThreads;
+    double rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + u * kCholThreads;
+      const int i = min(e % NMAX, n - 1), j = min(e / NMAX, n - 1);
+      rv[u] = a.Rs[i + j * n];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + u * kCholThreads;
+      const int i = e % NMAX, j = e / NMAX;
+      Rsl[i * kCLd + j] = (i <= j && j < n) ? rv[u] : 0.0;
       Ts[i * kCLd + j] = 0.0;
       if (i > j) Gs[i * kCLd + j] = 0.0;
     }
@@ -178,31 +191,28 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r)
         g[r] = (lane < 16) ? Gs[(base + r) * kCLd + base + lane] : (lane - 16 == r ? 1.0 : 0.0);
+      // Branch-free: a failed pivot only records its index (the first one);
+      // the values computed after it are never used.
       int bad = -1;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        if (bad < 0) {
-          const double d = readlane_d(g[k], k);
-          if (!(d > 0.0) || !__builtin_isfinite(d)) {
-            bad = base + k;
-          } else {
-            // Coupled Newton iteration for sqrt(d) and 1/sqrt(d) from the
-            // hardware estimate (two steps), then a residual correction.
-            const double y0 = __builtin_amdgcn_rsq(d);
-            double gq = d * y0, hq = 0.5 * y0;
+        const double d = readlane_d(g[k], k);
+        if (bad < 0 && (!(d > 0.0) || !__builtin_isfinite(d))) bad = base + k;
+        // Coupled Newton iteration for sqrt(d) and 1/sqrt(d) from the hardware
+        // estimate (two steps), then a residual correction.
+        const double y0 = __builtin_amdgcn_rsq(d);
+        double gq = d * y0, hq = 0.5 * y0;
 #pragma unroll
-            for (int it = 0; it < 2; ++it) {
-              const double rr = __builtin_fma(-hq, gq, 0.5);
-              gq = __builtin_fma(gq, rr, gq);
-              hq = __builtin_fma(hq, rr, hq);
-            }
-            const double rkk = __builtin_fma(__builtin_fma(-gq, gq, d), hq, gq);  // R(k,k)
-            const double y = 2.0 * hq;                                           // 1 / R(k,k)
-            g[k] = (lane == k) ? rkk : g[k] * y;
-#pragma unroll
-            for (int i = k + 1; i < 16; ++i) g[i] = __builtin_fma(-readlane_d(g[k], i), g[k], g[i]);
-          }
+        for (int it = 0; it < 2; ++it) {
+          const double rr = __builtin_fma(-hq, gq, 0.5);
+          gq = __builtin_fma(gq, rr, gq);
+          hq = __builtin_fma(hq, rr, hq);
         }
+        const double rkk = __builtin_fma(__builtin_fma(-gq, gq, d), hq, gq);  // R(k,k)
+        const double y = 2.0 * hq;                                           // 1 / R(k,k)
+        g[k] = (lane == k) ? rkk : g[k] * y;
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) g[i] = __builtin_fma(-readlane_d(g[k], i), g[k], g[i]);
       }
       if (lane < 16) {
 #pragma unroll
