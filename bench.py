@@ -250,27 +250,31 @@ def main():
                    sample=f"{runs} full oracle factorizations of the same {m}x{n} input, s={s} "
                           f"({runs * dt:.1f} s of CPU work)")
 
-    # Refined precision on the same input: FP32 Gram in pass 1, FP64 Cholesky-QR second pass.
+    # Refined precisions on the same input: lower-precision Gram in pass 1, FP64
+    # Cholesky-QR second pass.
     ws_r = torch.empty(rq.workspace_bytes(m, n, s, rq.FP32_REFINE), dtype=torch.uint8, device=dev)
+    mixed = {}
+    for pname in ("FP32_REFINE", "BF16X2_REFINE"):
+        prec = getattr(rq, pname)
 
-    def step_refine():
-        rq.factor(A, s, 0, Q=Q, R=R, workspace=ws_r, info=info, check=False, precision=rq.FP32_REFINE)
+        def step_refine():
+            rq.factor(A, s, 0, Q=Q, R=R, workspace=ws_r, info=info, check=False, precision=prec)
 
-    for _ in range(args.warmup):
-        step_refine()
-    torch.cuda.synchronize()
-    assert info.cpu().tolist() == [0, -1], info
-    e0.record(stream)
-    for _ in range(args.steps):
-        step_refine()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_r = e0.elapsed_time(e1) / args.steps
-    mixed = dict(precision="FP32_REFINE", ms_per_factorization=ms_r, value_GBps=bytes_alg / (ms_r * 1e-3) / 1e9,
-                 factorizations_per_s=1e3 / ms_r, speed_vs_fp64=ms / ms_r,
-                 orth=metrics.orth_error(Q), residual=metrics.residual(A, Q, R))
-    print(f"# FP32_REFINE: {ms_r * 1e3:.1f} us/factorization, orth {mixed['orth']:.1e}, "
-          f"residual {mixed['residual']:.1e}", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            step_refine()
+        torch.cuda.synchronize()
+        assert info.cpu().tolist() == [0, -1], info
+        e0.record(stream)
+        for _ in range(args.steps):
+            step_refine()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_r = e0.elapsed_time(e1) / args.steps
+        mixed[pname] = dict(ms_per_factorization=ms_r, value_GBps=bytes_alg / (ms_r * 1e-3) / 1e9,
+                            factorizations_per_s=1e3 / ms_r, speed_vs_fp64=ms / ms_r,
+                            orth=metrics.orth_error(Q), residual=metrics.residual(A, Q, R))
+        print(f"# {pname}: {ms_r * 1e3:.1f} us/factorization, orth {mixed[pname]['orth']:.1e}, "
+              f"residual {mixed[pname]['residual']:.1e}", file=sys.stderr, flush=True)
     del ws_r
     step()  # leave the FP64 result in Q, R
 

@@ -62,7 +62,10 @@ typedef enum {
  *       is removed by a second, binary64 Cholesky-QR pass on Q1 (Cholesky-QR2,
  *       Section 1): G = Q1^T Q1 = R3^T R3, Q = Q1 R3^{-1}, R = R3 (R2 R_s).
  *       Needs a larger workspace (rpcholqr_workspace_bytes with this value).
- *   RPCHOLQR_BF16X2_REFINE reserved; returns RPCHOLQR_EUNSUPPORTED. */
+ *   RPCHOLQR_BF16X2_REFINE as RPCHOLQR_FP32_REFINE, but step 5 splits each
+ *       float-rounded entry of A1 into bfloat16 hi + lo and forms
+ *       hi^T hi + hi^T lo + lo^T hi with float accumulation (about 16
+ *       significant bits); the second pass is the same binary64 pass. */
 typedef enum {
   RPCHOLQR_FP64 = 0,
   RPCHOLQR_FP32_REFINE = 1,

@@ -17,6 +17,7 @@ constexpr int kWaitVm0 = 0x0F70;    // vmcnt(0) only
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter form: output number
 // r of the generator seeded with `seed` is mix64(seed + (r+1)*golden_gamma).

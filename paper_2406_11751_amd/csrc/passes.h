@@ -27,8 +27,8 @@ namespace rpq {
 
 constexpr int kPassThreads = 256;
 constexpr int kPassWaves = kPassThreads / kWave;
-constexpr int kTriGroup = 16;  // triangle values per pipelined group in trsm_row
-constexpr int kTriSync = 8;    // groups between workgroup barriers in trsm_row
+constexpr int kTriGroup = 32;  // triangle values per pipelined group in trsm_row
+constexpr int kTriSync = 4;    // groups between workgroup barriers in trsm_row
 
 template <int NMAX>
 struct GramShape {
@@ -91,11 +91,21 @@ __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[N
 // MODE kSolveGram: A1 = A R_s^{-1} (stored in W) and its Gram partial.
 // MODE kGramOnly:  the Gram partial of A itself (used for Q1 in the second
 //                  Cholesky-QR pass of the refined precisions).
-// GP: arithmetic of the Gram contraction, FP64 (v_mfma_f64_16x16x4f64) or FP32
-//     (A1 rounded to float, v_mfma_f32_16x16x4f32, FP32 accumulation).
+// GP: arithmetic of the Gram contraction: FP64 (v_mfma_f64_16x16x4f64); FP32
+//     (A1 rounded to float, v_mfma_f32_16x16x4f32, FP32 accumulation); or BF16x2
+//     (A1 rounded to float and split into bfloat16 hi + lo, G ~ hi^T hi +
+//     hi^T lo + lo^T hi on v_mfma_f32_16x16x16bf16_1k, FP32 accumulation).
 // LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 elements.
 constexpr int kSolveGram = 0, kGramOnly = 1;
-constexpr int kGramF64 = 0, kGramF32 = 1;
+constexpr int kBfLdr = 36;  // bf16 elements per column in the BF16x2 staging (32 rows + pad)
+
+// bfloat16 of a float, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+constexpr int kGramF64 = 0, kGramF32 = 1, kGramBF16x2 = 2;
 
 template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
 __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk) {
@@ -105,6 +115,7 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
   constexpr int XS = 32 * LDX;  // doubles per wave
   constexpr int LDS_D = (kPassWaves * XS > kPassWaves * E) ? kPassWaves * XS : kPassWaves * E;
   using Acc = std::conditional_t<GP == kGramF64, d4, f4>;
+  static_assert(GP != kGramBF16x2 || 2 * NMAX * kBfLdr * 2 <= XS * 8, "bf16 staging fits the half-panel buffer");
   __shared__ double lds[LDS_D];
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
@@ -151,6 +162,43 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
 #pragma unroll
             for (int bj = bi; bj < NB; ++bj) {
               acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[tt], 0, 0, 0);
+              ++tt;
+            }
+        }
+      } else if constexpr (GP == kGramBF16x2) {
+        // Half panel column-major in LDS, hi and lo planes, element (r, c) at
+        // c * kBfLdr + r: a lane's four consecutive rows of a column are one
+        // 8-byte read, and 16 columns apart land in distinct banks.
+        uint16_t* xh = reinterpret_cast<uint16_t*>(xs);
+        uint16_t* xl = xh + NMAX * kBfLdr;
+        wave_lds_fence();
+        if ((lane >> 5) == h) {
+#pragma unroll
+          for (int j = 0; j < NMAX; ++j) {
+            const float f = (float)t[j];
+            const uint16_t hi = bf16_rne(f);
+            xh[j * kBfLdr + half_row] = hi;
+            xl[j * kBfLdr + half_row] = bf16_rne(f - bf16_to_float(hi));
+          }
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {  // 16-row chunks of the half panel
+          s4 vh[NB], vl[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int off = (16 * b + cq) * kBfLdr + 16 * kk + 4 * rq;
+            vh[b] = *reinterpret_cast<const s4*>(xh + off);
+            vl[b] = *reinterpret_cast<const s4*>(xl + off);
+          }
+          int tt = 0;
+#pragma unroll
+          for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj) {
+              acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vh[bi], vh[bj], acc[tt], 0, 0, 0);
+              acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vh[bi], vl[bj], acc[tt], 0, 0, 0);
+              acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vl[bi], vh[bj], acc[tt], 0, 0, 0);
               ++tt;
             }
         }

@@ -190,7 +190,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
   if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
-  const bool refine = precision == RPCHOLQR_FP32_REFINE;
+  const bool refine = precision == RPCHOLQR_FP32_REFINE || precision == RPCHOLQR_BF16X2_REFINE;
   if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
   Plan p;
   if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, refine)) return RPCHOLQR_EUNSUPPORTED;
@@ -255,7 +255,12 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   int pa_grid = 0;
   with_nmax(p.nmax, [&](auto nm) {
     constexpr int NM = decltype(nm)::value;
-    pa_grid = refine ? launch_passes_A<NM, kSolveGram, kGramF32>(p, pa, st) : launch_passes_A<NM>(p, pa, st);
+    if (precision == RPCHOLQR_FP32_REFINE)
+      pa_grid = launch_passes_A<NM, kSolveGram, kGramF32>(p, pa, st);
+    else if (precision == RPCHOLQR_BF16X2_REFINE)
+      pa_grid = launch_passes_A<NM, kSolveGram, kGramBF16x2>(p, pa, st);
+    else
+      pa_grid = launch_passes_A<NM>(p, pa, st);
   });
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   const int g2 = (pa_grid + kReduceChunk - 1) / kReduceChunk;  // <= p.G2
@@ -638,9 +643,10 @@ extern "C" {
 int32_t rpcholqr_max_n(void) { return kMaxN; }
 
 size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision) {
-  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE) return 0;
+  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
+    return 0;
   Plan p;
-  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, precision == RPCHOLQR_FP32_REFINE)) return 0;
+  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, precision != RPCHOLQR_FP64)) return 0;
   return p.total;
 }
 

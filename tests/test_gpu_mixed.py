@@ -1,9 +1,10 @@
-"""GPU parity of the refined precision RPCHOLQR_FP32_REFINE against the FP64 oracle.
+"""GPU parity of the refined precisions (RPCHOLQR_FP32_REFINE, RPCHOLQR_BF16X2_REFINE)
+against the FP64 oracle.
 
 Pass 1 keeps the FP64 row solves, so the sampled indices, A_s, R_s and A1 are
-bit-identical to the oracle's; its Gram matrix is formed in FP32 and is checked
-against an FP32 emulation and against the FP64 Gram at the FP32 rounding
-level.  After the FP64 second pass, Q and R must agree with the FP64 oracle
+bit-identical to the oracle's; its Gram matrix is formed in FP32 (or from a
+bfloat16 hi + lo split) and is checked against a numpy emulation of that
+arithmetic and against the FP64 Gram at the corresponding rounding level.  After the FP64 second pass, Q and R must agree with the FP64 oracle
 within 1e-12 relative Frobenius error, with orth <= 1e-12 and residual <= 1e-15.
 """
 import os
@@ -47,56 +48,77 @@ CASES = [
 ]
 
 
-def check_refine(A_h, s, seed):
+def bf16_split(f):
+    """hi = bfloat16(f) (round to nearest even), lo = bfloat16(f - hi), as float32."""
+    def rne(x):
+        u = x.view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+        return u.astype(np.uint32).view(np.float32)
+    hi = rne(np.ascontiguousarray(f, dtype=np.float32))
+    lo = rne(np.ascontiguousarray(f - hi, dtype=np.float32))
+    return hi, lo
+
+
+def emulated_gram(a1, prec):
+    f = a1.astype(np.float32)
+    if prec == rq().FP32_REFINE:
+        return np.triu((f.T @ f).astype(np.float64))
+    hi, lo = (x.astype(np.float64) for x in bf16_split(f))
+    return np.triu(hi.T @ hi + hi.T @ lo + lo.T @ hi)
+
+
+def check_refine(A_h, s, seed, prec):
     m, n = A_h.shape
-    announce(f"FP32_REFINE m={m} n={n} s={s} seed={seed}")
-    Q, R, info, ex = rq().factor(dev(A_h), s, seed, precision=rq().FP32_REFINE, debug=True)
+    announce(f"precision {prec} m={m} n={n} s={s} seed={seed}")
+    Q, R, info, ex = rq().factor(dev(A_h), s, seed, precision=prec, debug=True)
     ref = oracle.rpcholqr(A_h, s, seed, nthreads=NTHREADS)
     assert np.array_equal(host(ex["idx"]), ref.idx)
     assert np.array_equal(host(ex["Rs"]), ref.Rs)
     a1 = host(ex["A1"])
     assert np.array_equal(a1, ref.A1), "A1 differs"
-    # pass-1 Gram: FP32 arithmetic on A1 rounded to float
+    # pass-1 Gram in the lower precision
     g1 = np.triu(host(ex["G1"]))
-    a1f = a1.astype(np.float32)
-    g32 = np.triu((a1f.T @ a1f).astype(np.float64))
     scale = max(1.0, float(np.abs(ref.G1).max()))
     # both sums carry about sqrt(rows) float roundings of size 2^-24 relative to |G1|
-    assert np.abs(g1 - g32).max() / scale < 8 * np.sqrt(m) * 2.0**-24 + 1e-6
-    assert metrics.rel_fro(g1, np.triu(ref.G1)) < 1e-5
+    assert np.abs(g1 - emulated_gram(a1, prec)).max() / scale < 8 * np.sqrt(m) * 2.0**-24 + 1e-6
+    dg = metrics.rel_fro(g1, np.triu(ref.G1))
+    assert dg < (1e-5 if prec == rq().FP32_REFINE else 1e-3)
     Qh, Rh = host(Q), host(R)
     eq, er = metrics.rel_fro(Qh, ref.Q), metrics.rel_fro(Rh, ref.R)
     orth, res = metrics.orth_error(Qh), metrics.residual(A_h, Qh, Rh)
-    print(f"  |dQ|={eq:.2e} |dR|={er:.2e} orth={orth:.2e} res={res:.2e} |dG1|={metrics.rel_fro(g1, np.triu(ref.G1)):.1e}",
-          flush=True)
+    print(f"  |dQ|={eq:.2e} |dR|={er:.2e} orth={orth:.2e} res={res:.2e} |dG1|={dg:.1e}", flush=True)
     assert eq < TOL and er < TOL
     assert orth < (1e-12 if s >= 2 * n else 1e-10) and res < 1e-15
     assert np.array_equal(np.tril(Rh, -1), np.zeros((n, n)))
 
 
+@pytest.mark.parametrize("prec", ["FP32_REFINE", "BF16X2_REFINE"])
 @pytest.mark.parametrize("m,n,s,kappa,seed", CASES)
-def test_fp32_refine_small(m, n, s, kappa, seed):
-    check_refine(gen_usv(m, n, kappa, 200 + seed), s, seed)
+def test_refine_small(m, n, s, kappa, seed, prec):
+    check_refine(gen_usv(m, n, kappa, 200 + seed), s, seed, getattr(rq(), prec))
 
 
-def test_fp32_refine_full_size():
+def test_refine_full_size():
     m, n, s = 1_000_000, 64, 192
     A_h = gen_usv(m, n, 1e12, 0)
-    announce("FP32_REFINE 1e6 x 64")
     A = dev(A_h)
-    Q, R, _ = rq().factor(A, s, 0, precision=rq().FP32_REFINE)
     ref = oracle.rpcholqr(A_h, s, 0, nthreads=NTHREADS)
-    assert metrics.rel_fro(host(Q), ref.Q) < TOL and metrics.rel_fro(host(R), ref.R) < TOL
-    assert metrics.orth_error(Q) < 1e-12 and metrics.residual(A, Q, R) < 1e-15
+    for prec in (rq().FP32_REFINE, rq().BF16X2_REFINE):
+        announce(f"precision {prec} 1e6 x 64")
+        Q, R, _ = rq().factor(A, s, 0, precision=prec)
+        assert metrics.rel_fro(host(Q), ref.Q) < TOL and metrics.rel_fro(host(R), ref.R) < TOL
+        assert metrics.orth_error(Q) < 1e-12 and metrics.residual(A, Q, R) < 1e-15
 
 
 def test_refine_workspace_and_unsupported():
     lib = rq().load_library()
     assert rq().workspace_bytes(10000, 50, 150, rq().FP32_REFINE) > rq().workspace_bytes(10000, 50, 150)
-    assert rq().workspace_bytes(10000, 50, 150, rq().BF16X2_REFINE) == 0
+    assert rq().workspace_bytes(10000, 50, 150, rq().BF16X2_REFINE) == rq().workspace_bytes(10000, 50, 150,
+                                                                                              rq().FP32_REFINE)
+    assert rq().workspace_bytes(10000, 50, 150, 7) == 0
     A = dev(gen_usv(1000, 8, 10.0, 1))
     with pytest.raises(rq().RpCholQRError):
-        rq().factor(A, 24, 0, precision=rq().BF16X2_REFINE)
+        rq().factor(A, 24, 0, precision=7)
     # a workspace sized for FP64 is too small for the refined precision
     ws = torch.empty(rq().workspace_bytes(1000, 8, 24), dtype=torch.uint8, device="cuda")
     Q = rq().colmajor_empty(1000, 8, "cuda")

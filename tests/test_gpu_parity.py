@@ -191,7 +191,7 @@ def test_argument_errors():
     assert call(Q_=A) == -1                       # Q overlaps A
     assert call(wsb=nb - 8) == -3
     assert call(prec=1) == -3                    # FP32_REFINE needs a larger workspace
-    assert call(prec=2) == -4
+    assert call(prec=2) == -3                    # BF16X2_REFINE likewise
     assert call(prec=7) == -4
     big_n = rq().max_n() + 1
     assert lib.rpcholqr_factor(10 * big_n, big_n, 3 * big_n, 0, P(A), 10 * big_n, P(Q), 10 * big_n, P(R), big_n,
