@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="bounded CPU sample: repeat oracle factorizations for about this long")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the refined-precision measurement")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (for counter calibration)")
@@ -253,8 +254,8 @@ def main():
     # Refined precisions on the same input: lower-precision Gram in pass 1, FP64
     # Cholesky-QR second pass.
     ws_r = torch.empty(rq.workspace_bytes(m, n, s, rq.FP32_REFINE), dtype=torch.uint8, device=dev)
-    mixed = {}
-    for pname in ("FP32_REFINE", "BF16X2_REFINE"):
+    mixed = None if args.no_mixed else {}
+    for pname in () if args.no_mixed else ("FP32_REFINE", "BF16X2_REFINE"):
         prec = getattr(rq, pname)
 
         def step_refine():

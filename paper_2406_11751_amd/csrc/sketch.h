@@ -125,9 +125,11 @@ __device__ __forceinline__ void sketch_status(const SketchArgs& a, int bad_k) {
 }
 
 // Line 3 with the sample in registers: RPT rows per lane (s <= 16 RPT), n <= 64.
-// One barrier per Householder step: during step k every wave applies reflector
-// k to its four columns, and the wave owning column k+1 then forms reflector
-// k+1 from the freshly updated column into the other LDS buffer.
+// Wave w owns columns 4w .. 4w+3, one per 16-lane group; lane l16 of a group
+// holds rows l16 + 16 t in slot t.  One barrier per Householder step: during
+// step k every wave applies reflector k to its columns that are not final yet,
+// and the wave owning column k+1 then forms reflector k+1 from the freshly
+// updated column into the other LDS buffer.
 template <int RPT>
 __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
   __shared__ double vbuf[2][16 * RPT];
@@ -140,7 +142,7 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int l16 = lane & 15, q = lane >> 4;
-  const int j = wave + 16 * q;  // my column
+  const int j = 4 * wave + q;  // my column: each wave owns four consecutive columns
   const int n = a.n, s = a.s;
 
   for (int e = threadIdx.x; e < kSketchMaxN * kSketchLdr; e += kSketchThreads) Rl[e] = 0.0;
@@ -153,8 +155,8 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
   }
   __syncthreads();
 
-  // Reflector k from my column (this wave owns column k; its row KB = k / 16
-  // holds it, row k of it sits in lane k, slot KB).
+  // Reflector k from my column (this wave owns column k, in lane group k mod 4;
+  // row k of it sits in lane k mod 16 of that group, slot KB = k / 16).
   auto reflector = [&](auto kb, int k) __attribute__((always_inline)) {
     constexpr int KB = decltype(kb)::value;
     const int buf = k & 1;
@@ -165,8 +167,10 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
       const double x = (r >= k) ? W[t] : 0.0;
       p = __builtin_fma(x, x, p);
     }
-    const double nu2 = readlane_d(row16_sum(p), k);
-    const double alpha = readlane_d(W[KB], k);
+    // Row k of column k sits in lane k mod 16 of the owner's group k mod 4.
+    const int owner_lane = 16 * (k & 3) + (k & 15);
+    const double nu2 = readlane_d(row16_sum(p), owner_lane);
+    const double alpha = readlane_d(W[KB], owner_lane);
     if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
       if (lane == 0) bad[buf] = k;
       return;
@@ -175,7 +179,7 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     const double beta = (alpha >= 0.0) ? -nu : nu;
     const double d = 1.0 / (alpha - beta);
     const double tau = (beta - alpha) / beta;
-    if (q == KB) {
+    if (q == (k & 3)) {
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int r = l16 + 16 * t;
@@ -217,8 +221,10 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 16 * KB + kk;
       if (k >= n || bad[k & 1] >= 0) break;
-      apply(std::integral_constant<int, KB>{}, k);
-      if (k + 1 < n && wave == ((k + 1) & 15)) {
+      // Columns j <= k are final (reflector k would only add exact zeros to
+      // them); waves whose four columns are all final idle until the barrier.
+      if (j > k && j < n) apply(std::integral_constant<int, KB>{}, k);
+      if (k + 1 < n && wave == ((k + 1) >> 2)) {
         if (kk < 15)
           reflector(std::integral_constant<int, KB>{}, k + 1);
         else if constexpr (KB < 3)
@@ -244,7 +250,7 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int l16 = lane & 15, q = lane >> 4;
-  const int j = wave + 16 * q;
+  const int j = 4 * wave + q;  // as in k_sketch_qr
   const int n = a.n, s = a.s;
   const bool mine = j < n;
   double* W = a.As + (int64_t)(mine ? j : 0) * s;  // my column (padding columns never write)
@@ -255,7 +261,7 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
 
   for (int k = -1; k < n; ++k) {
     if (k >= 0 && bad[k & 1] >= 0) break;
-    if (k >= 0) {
+    if (k >= 0 && j > k && mine) {
       const int buf = k & 1;
       const double* vb = vdyn + (size_t)buf * s;
       const double tau = tau_s[buf];
@@ -272,15 +278,16 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
       }
     }
     const int k1 = k + 1;
-    if (k1 < n && wave == (k1 & 15)) {
-      // Column k1 lives in row k1 / 16 of this wave; its row k1 is held by lane k1.
+    if (k1 < n && wave == (k1 >> 2)) {
+      // Column k1 is lane group k1 mod 4 of this wave; its row k1 is in lane k1 mod 16 of that group.
       double p = 0.0;
       for (int r = l16; r < s; r += 16) {
         const double x = (r >= k1 && mine) ? W[r] : 0.0;
         p = __builtin_fma(x, x, p);
       }
-      const double nu2 = readlane_d(row16_sum(p), k1);
-      const double alpha = readlane_d(lane == k1 ? W[k1] : 0.0, k1);
+      const int owner_lane = 16 * (k1 & 3) + (k1 & 15);
+      const double nu2 = readlane_d(row16_sum(p), owner_lane);
+      const double alpha = readlane_d(lane == owner_lane ? W[k1] : 0.0, owner_lane);
       if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
         if (lane == 0) bad[k1 & 1] = k1;
       } else {
@@ -289,7 +296,7 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
         const double d = 1.0 / (alpha - beta);
         const double tau = (beta - alpha) / beta;
         double* vb = vdyn + (size_t)(k1 & 1) * s;
-        if (q == (k1 >> 4))
+        if (q == (k1 & 3))
           for (int r = l16; r < s; r += 16)
             if (r >= k1) vb[r] = (r == k1) ? 1.0 : W[r] * d;
         if (lane == 0) {
