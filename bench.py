@@ -72,10 +72,10 @@ def measured_traffic(pass_name: str, m: int, n: int):
 
 def batched_measurement(args, torch, rq, gen_usv, metrics):
     """Batched workload: the 2048-problem list (m ~ U{2000..200000}, n ~ U{8, 16,
-    32, 64, 128}, log10 kappa ~ U[2, 14], s = 3n, seed i) without its n = 128
-    problems (beyond this build's largest n), generated on the GPU.  Times whole
-    executions of one batched plan and, for comparison, the same problems
-    factored one call at a time with the single-problem entry point."""
+    32, 64, 128}, log10 kappa ~ U[2, 14], s = 3n, seed i), generated on the GPU
+    (problems beyond the library's largest n, if any, are left out and counted).
+    Times whole executions of one batched plan and, for comparison, the same
+    problems factored one call at a time with the single-problem entry point."""
     from workloads import batched_problem_list
 
     dev = torch.device("cuda:0")
@@ -113,9 +113,10 @@ def batched_measurement(args, torch, rq, gen_usv, metrics):
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1)
     bytes_alg = sum(24.0 * p["m"] * p["n"] for p in keep)
+    excluded = len(plist) - len(keep)
     out = dict(workload="2048-problem list (m ~ U{2000..200000}, n ~ U{8,16,32,64,128}, log10 kappa ~ U[2,14], "
-                        "s = 3n, seed i), n = 128 problems excluded",
-               problems=len(keep), excluded_n128=len(plist) - len(keep), ms_per_batch=ms,
+                        "s = 3n, seed i)" + (f", {excluded} problems with n > {rq.max_n()} excluded" if excluded else ""),
+               problems=len(keep), excluded=excluded, ms_per_batch=ms,
                factorizations_per_s=len(keep) / (ms * 1e-3), value_GBps=bytes_alg / (ms * 1e-3) / 1e9,
                sequential_single_calls_ms=seq_ms, speedup_vs_single_calls=seq_ms / ms,
                max_orth_every_64th=orth, device_bytes=plan.device_bytes)

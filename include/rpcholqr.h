@@ -87,7 +87,9 @@ typedef struct {
 /* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
 #define RPCHOLQR_INFO_ECHOL2 3
 
-/* Largest n this build accepts. */
+/* Largest n this build accepts (128).  Sizes this build supports: s <= 1536
+ * and n <= 128 for RPCHOLQR_FP64, n <= 64 for the refined precisions; other
+ * sizes give RPCHOLQR_EUNSUPPORTED. */
 int32_t rpcholqr_max_n(void);
 
 /* Device workspace in bytes needed by rpcholqr_factor / rpcholqr_factor_debug

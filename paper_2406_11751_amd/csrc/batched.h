@@ -8,6 +8,7 @@
 #include "passes.h"
 #include "sketch.h"
 #include "small.h"
+#include "wide.h"
 
 namespace rpq {
 
@@ -31,13 +32,14 @@ __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr(const SketchArgs*
   sketch_qr_body<RPT>(a);
 }
 
+template <int MAXN>
 __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr_generic(const SketchArgs* __restrict__ args,
                                                                        const int32_t* __restrict__ probs,
                                                                        int32_t* info) {
   const int p = probs[blockIdx.x];
   SketchArgs a = args[p];
   a.info = info + 2 * p;
-  sketch_qr_generic_body(a);
+  sketch_qr_generic_body<MAXN>(a);
 }
 
 template <int NMAX>
@@ -65,6 +67,31 @@ __global__ __launch_bounds__(kPassBThreads) void kb_passB(const PassBArgs* __res
   PassBArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
   passB_body<NMAX>(a, it.local, it.count);
+}
+
+template <int HALF>
+__global__ __launch_bounds__(kPassThreads, 2) void kb_passW(const PassAArgs* __restrict__ args,
+                                                           const BatchItem* __restrict__ items, int32_t* info) {
+  const BatchItem it = items[blockIdx.x];
+  PassAArgs a = args[it.problem];
+  a.info = info + 2 * it.problem;
+  passW_body<HALF>(a, it.local, it.count);
+}
+
+__global__ __launch_bounds__(kPassThreads) void kb_gramW(const PassAArgs* __restrict__ args,
+                                                        const BatchItem* __restrict__ items, int32_t* info) {
+  const BatchItem it = items[blockIdx.x];
+  PassAArgs a = args[it.problem];
+  a.info = info + 2 * it.problem;
+  gramW_body(a, it.local, it.count);
+}
+
+__global__ __launch_bounds__(kPassB128Threads) void kb_passB128(const PassBArgs* __restrict__ args,
+                                                               const BatchItem* __restrict__ items, int32_t* info) {
+  const BatchItem it = items[blockIdx.x];
+  PassBArgs a = args[it.problem];
+  a.info = info + 2 * it.problem;
+  passB128_body(a, it.local, it.count);
 }
 
 }  // namespace rpq

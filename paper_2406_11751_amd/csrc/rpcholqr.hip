@@ -18,13 +18,15 @@
 #include "passes.h"
 #include "sketch.h"
 #include "small.h"
+#include "wide.h"
 #include "batched.h"
 
 namespace {
 
 using namespace rpq;
 
-constexpr int kMaxN = 64;
+constexpr int kMaxN = 128;
+constexpr int kWideN = 128;  // column class of 64 < n <= 128 (two-half row solve, separate Gram pass)
 constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles in LDS
 constexpr int kPassAMaxBlocks = 512;
 static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
@@ -48,7 +50,8 @@ int pick_nmax(int64_t n) {
   if (n <= 16) return 16;
   if (n <= 32) return 32;
   if (n <= 48) return 48;
-  return 64;
+  if (n <= 64) return 64;
+  return kWideN;
 }
 
 // Workspace layout of one problem.  pa_cap bounds the number of pass-A
@@ -58,6 +61,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
                bool direct_partials = false, bool refine = false) {
   if (n < 1 || m < n || s < n || n > kMaxN) return false;
   p->nmax = pick_nmax(n);
+  if (p->nmax == kWideN && refine) return false;  // refined precisions: n <= 64
   p->NB = (p->nmax + 15) / 16;
   p->E = p->NB * (p->NB + 1) / 2 * 256;
   p->panels = (m + kWave - 1) / kWave;
@@ -68,7 +72,10 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
   p->G2 = direct_partials ? p->PA : (p->PA + kReduceChunk - 1) / kReduceChunk;
   const int64_t rows = (s + 15) / 16;
   p->rpt = rows <= 4 ? 4 : rows <= 8 ? 8 : rows <= 12 ? 12 : rows <= 16 ? 16 : rows <= 24 ? 24 : 0;
+  if (p->nmax == kWideN) p->rpt = 0;  // the register sketch kernels hold 64 columns
   if (p->rpt == 0 && s > kMaxSketchRows) return false;
+  // nmax <= 64: one packed triangle; nmax = 128: R11, R22 packed and R12 64 x 64,
+  // 2 * 2080 + 4096 = 128 * 129 / 2 doubles as well.
   const size_t tri = (size_t)p->nmax * (p->nmax + 1) / 2 * sizeof(double);
   size_t off = 0;
   p->off_tri = off;
@@ -107,7 +114,10 @@ void launch_sketch(const Plan& p, const SketchArgs& a, hipStream_t st) {
     case 16: hipLaunchKernelGGL((k_sketch_qr<16>), dim3(1), blk, 0, st, a); break;
     case 24: hipLaunchKernelGGL((k_sketch_qr<24>), dim3(1), blk, 0, st, a); break;
     default:
-      hipLaunchKernelGGL(k_sketch_qr_generic, dim3(1), blk, 2 * (size_t)a.s * sizeof(double), st, a);
+      if (p.nmax == kWideN)
+        hipLaunchKernelGGL((k_sketch_qr_generic<kWideN>), dim3(1), blk, 2 * (size_t)a.s * sizeof(double), st, a);
+      else
+        hipLaunchKernelGGL((k_sketch_qr_generic<64>), dim3(1), blk, 2 * (size_t)a.s * sizeof(double), st, a);
       break;
   }
 }
@@ -151,6 +161,24 @@ int launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
 template <int NMAX>
 void launch_pass_B(const Plan& p, const PassBArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_passB<NMAX>), dim3(p.PB), dim3(kPassBThreads), 0, st, a);
+}
+
+// Pass A for 64 < n <= 128: both halves of the row solve, then the Gram pass.
+// Returns the number of Gram partials written.
+int launch_passes_A_wide(const Plan& p, const PassAArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_passW<0>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL((k_passW<1>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL(k_gramW, dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  return p.PA;
+}
+
+// Pass B for 64 < n <= 128: R2^{-1} takes 128 KB of LDS, one workgroup per CU.
+void launch_pass_B_wide(int64_t m, const PassBArgs& a, hipStream_t st) {
+  const int64_t groups = ((m + 15) / 16 + kPassB128Waves - 1) / kPassB128Waves;
+  const int cus = device_cus();
+  const int64_t cap = cus > 0 ? cus : 256;
+  const int64_t grid = groups < cap ? groups : cap;
+  hipLaunchKernelGGL(k_passB128, dim3((unsigned)grid), dim3(kPassB128Threads), 0, st, a);
 }
 
 // Event timing (rpcholqr_timing_*): one set of NSTAGES+1 events per recorded call.
@@ -253,7 +281,9 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pa.W = Q;
   pa.ldw = ldq;
   int pa_grid = 0;
-  with_nmax(p.nmax, [&](auto nm) {
+  if (p.nmax == kWideN) {
+    pa_grid = launch_passes_A_wide(p, pa, st);
+  } else with_nmax(p.nmax, [&](auto nm) {
     constexpr int NM = decltype(nm)::value;
     if (precision == RPCHOLQR_FP32_REFINE)
       pa_grid = launch_passes_A<NM, kSolveGram, kGramF32>(p, pa, st);
@@ -291,6 +321,10 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   ca.R2_out = R2;
   ca.fail_code = RPCHOLQR_INFO_ECHOL;
   auto cholesky = [&](const CholArgs& c) {
+    if (p.nmax == kWideN) {
+      hipLaunchKernelGGL((k_cholesky<kWideN>), dim3(1), dim3(kCholThreads), 0, st, c);
+      return;
+    }
     with_nmax(p.nmax, [&](auto nm) {
       constexpr int NM = decltype(nm)::value;
       hipLaunchKernelGGL((k_cholesky<NM>), dim3(1), dim3(kCholThreads), 0, st, c);
@@ -309,7 +343,10 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   pb.ldq = ldq;
   pb.info = inf;
   auto pass_b = [&]() {
-    with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
+    if (p.nmax == kWideN)
+      launch_pass_B_wide(m, pb, st);
+    else
+      with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
   };
   pass_b();
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
@@ -352,8 +389,19 @@ constexpr int64_t kBatchPartialsMax = 64;   // pass-A workgroups (Gram partials)
 constexpr int64_t kBatchPgroupsPerWG = 8;   // target panel groups per pass-A workgroup
 constexpr int64_t kBatchBIters = 16;        // target 4-block iterations per pass-B workgroup
 
+// Sketch class of a problem: the register kernel's RPT, 0 for the generic
+// kernel with n <= 64, -1 for the generic kernel with n <= 128.
+int sketch_key(const Plan& p) { return p.nmax == kWideN ? -1 : p.rpt; }
+
+// 16-row blocks of pass B per workgroup and target iteration count.
+int64_t pass_b_items(int nmax, int64_t m) {
+  const int64_t blocks16 = (m + 15) / 16;
+  const int64_t per_wg = (int64_t)(nmax == kWideN ? kPassB128Waves : kPassBThreads / kWave) * kBatchBIters;
+  return std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
+}
+
 struct SizeClass {
-  int key = 0;                       // RPT (sketch classes) or NMAX (pass classes)
+  int key = 0;                       // sketch_key (sketch classes) or NMAX (pass classes)
   size_t probs_off = 0, items_a_off = 0, items_b_off = 0;  // offsets into the device buffer
   int nprobs = 0;
   int64_t items_a = 0, items_b = 0;
@@ -422,7 +470,7 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
   std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return m[x] > m[y]; });
   std::map<int, std::vector<int32_t>> by_rpt, by_nmax;
   for (int64_t b : order) {
-    by_rpt[plans[b].rpt].push_back((int32_t)b);
+    by_rpt[sketch_key(plans[b])].push_back((int32_t)b);
     by_nmax[plans[b].nmax].push_back((int32_t)b);
   }
   // Host images of the device tables.
@@ -464,9 +512,7 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
     c.probs_off = reserve(sizeof(int32_t) * kv.second.size());
     for (int32_t b : kv.second) {
       c.items_a += plans[b].PA;
-      const int64_t blocks16 = (m[b] + 15) / 16;
-      const int64_t per_wg = (int64_t)(kPassBThreads / kWave) * kBatchBIters;
-      c.items_b += std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
+      c.items_b += pass_b_items(plans[b].nmax, m[b]);
     }
     c.items_a_off = reserve(sizeof(BatchItem) * c.items_a);
     c.items_b_off = reserve(sizeof(BatchItem) * c.items_b);
@@ -552,9 +598,7 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
       for (int32_t b : kv.second) {
         const int32_t na = plans[b].PA;
         for (int32_t k = 0; k < na; ++k) items_a.push_back(BatchItem{b, k, na});
-        const int64_t blocks16 = (m[b] + 15) / 16;
-        const int64_t per_wg = (int64_t)(kPassBThreads / kWave) * kBatchBIters;
-        const int32_t nb = (int32_t)std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
+        const int32_t nb = (int32_t)pass_b_items(plans[b].nmax, m[b]);
         for (int32_t k = 0; k < nb; ++k) items_b.push_back(BatchItem{b, k, nb});
       }
       ok = ok &&
@@ -595,8 +639,12 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 12: hipLaunchKernelGGL((kb_sketch_qr<12>), g, blk, 0, st, sk, probs, inf); break;
       case 16: hipLaunchKernelGGL((kb_sketch_qr<16>), g, blk, 0, st, sk, probs, inf); break;
       case 24: hipLaunchKernelGGL((kb_sketch_qr<24>), g, blk, 0, st, sk, probs, inf); break;
+      case 0:
+        hipLaunchKernelGGL((kb_sketch_qr_generic<64>), g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs, inf);
+        break;
       default:
-        hipLaunchKernelGGL(kb_sketch_qr_generic, g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs, inf);
+        hipLaunchKernelGGL((kb_sketch_qr_generic<kWideN>), g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs,
+                           inf);
         break;
     }
   }
@@ -609,7 +657,12 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 16: hipLaunchKernelGGL((kb_passA<16>), g, blk, 0, st, pa, it, inf); break;
       case 32: hipLaunchKernelGGL((kb_passA<32>), g, blk, 0, st, pa, it, inf); break;
       case 48: hipLaunchKernelGGL((kb_passA<48>), g, blk, 0, st, pa, it, inf); break;
-      default: hipLaunchKernelGGL((kb_passA<64>), g, blk, 0, st, pa, it, inf); break;
+      case 64: hipLaunchKernelGGL((kb_passA<64>), g, blk, 0, st, pa, it, inf); break;
+      default:
+        hipLaunchKernelGGL((kb_passW<0>), g, blk, 0, st, pa, it, inf);
+        hipLaunchKernelGGL((kb_passW<1>), g, blk, 0, st, pa, it, inf);
+        hipLaunchKernelGGL(kb_gramW, g, blk, 0, st, pa, it, inf);
+        break;
     }
   }
   for (const SizeClass& c : p->pass_classes) {
@@ -619,7 +672,8 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 16: hipLaunchKernelGGL((kb_cholesky<16>), g, blk, 0, st, ch, probs, inf); break;
       case 32: hipLaunchKernelGGL((kb_cholesky<32>), g, blk, 0, st, ch, probs, inf); break;
       case 48: hipLaunchKernelGGL((kb_cholesky<48>), g, blk, 0, st, ch, probs, inf); break;
-      default: hipLaunchKernelGGL((kb_cholesky<64>), g, blk, 0, st, ch, probs, inf); break;
+      case 64: hipLaunchKernelGGL((kb_cholesky<64>), g, blk, 0, st, ch, probs, inf); break;
+      default: hipLaunchKernelGGL((kb_cholesky<kWideN>), g, blk, 0, st, ch, probs, inf); break;
     }
   }
   for (const SizeClass& c : p->pass_classes) {
@@ -629,7 +683,8 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 16: hipLaunchKernelGGL((kb_passB<16>), g, blk, 0, st, pb, it, inf); break;
       case 32: hipLaunchKernelGGL((kb_passB<32>), g, blk, 0, st, pb, it, inf); break;
       case 48: hipLaunchKernelGGL((kb_passB<48>), g, blk, 0, st, pb, it, inf); break;
-      default: hipLaunchKernelGGL((kb_passB<64>), g, blk, 0, st, pb, it, inf); break;
+      case 64: hipLaunchKernelGGL((kb_passB<64>), g, blk, 0, st, pb, it, inf); break;
+      default: hipLaunchKernelGGL(kb_passB128, g, dim3(kPassB128Threads), 0, st, pb, it, inf); break;
     }
   }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;

@@ -84,36 +84,47 @@ __device__ __forceinline__ double row16_sum(double p) {
 }
 
 // Sign-normalize R_s (negate rows with a negative diagonal; exact) and write
-// the packed triangle for the row solves, the column-major copy and the
-// optional output.
+// the triangle operands of the row solves, the column-major copy and the
+// optional output.  Rl holds R row-major with row stride LDR.
+//   nmax <= 64: one packed triangle (see Tri), nmax rows.
+//   nmax = 128: R11 packed (64 rows), R22 packed (64 rows, from row 64), then
+//               R12 = R(0:64, 64:128) row-major 64 x 64.
+template <int LDR>
 __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double* Rl) {
   const int n = a.n, nmax = a.nmax;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e % n, j = e / n;
     double v = 0.0;
     if (i <= j) {
-      v = Rl[i * kSketchLdr + j];
-      if (Rl[i * kSketchLdr + i] < 0.0) v = -v;
+      v = Rl[i * LDR + j];
+      if (Rl[i * LDR + i] < 0.0) v = -v;
     }
     a.Rs[e] = v;
     if (a.Rs_out) a.Rs_out[e] = v;
   }
-  for (int e = threadIdx.x; e < nmax * nmax; e += blockDim.x) {
-    const int k = e / nmax, j = e - k * nmax;
-    if (j < k) continue;
-    double v;
-    if (k < n && j < n) {
-      const double rkk = Rl[k * kSketchLdr + k];
-      if (j == k) {
-        v = 1.0 / (rkk < 0.0 ? -rkk : rkk);
-      } else {
-        v = Rl[k * kSketchLdr + j];
-        if (rkk < 0.0) v = -v;
-      }
-    } else {
-      v = (j == k) ? 1.0 : 0.0;
+  // element (k, j) of the sign-normalized R, identity beyond n
+  auto rn = [&](int k, int j) -> double {
+    if (k >= n || j >= n) return (j == k) ? 1.0 : 0.0;
+    const double rkk = Rl[k * LDR + k];
+    const double v = Rl[k * LDR + j];
+    return rkk < 0.0 ? -v : v;
+  };
+  auto put_packed = [&](double* dst, int k0, int w) {  // rows k0 .. k0+w-1, columns k0 ..
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+      const int k = e / w, j = e - k * w;
+      if (j < k) continue;
+      const double v = (j == k) ? 1.0 / rn(k0 + k, k0 + k) : rn(k0 + k, k0 + j);
+      dst[tri_row_start(k, w) + (j - k)] = v;
     }
-    a.tri[tri_row_start(k, nmax) + (j - k)] = v;
+  };
+  if (nmax <= 64) {
+    put_packed(a.tri, 0, nmax);
+  } else {
+    constexpr int H = 64;
+    put_packed(a.tri, 0, H);
+    put_packed(a.tri + H * (H + 1) / 2, H, H);
+    double* r12 = a.tri + H * (H + 1);
+    for (int e = threadIdx.x; e < H * H; e += blockDim.x) r12[e] = rn(e / H, H + e % H);
   }
 }
 
@@ -236,53 +247,62 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
   const int bad_k = bad[0] >= 0 ? bad[0] : bad[1];
   sketch_status(a, bad_k);
   if (bad_k >= 0) return;
-  sketch_finish(a, Rl);
+  sketch_finish<kSketchLdr>(a, Rl);
 }
 
-// Line 3 for large s: the same layout and operation order, with the sample
-// kept in global memory (a.As, worked on in place) and the Householder vector
-// in dynamic LDS (2 s doubles).  n <= 64.
+// Line 3 for large s or n > 64: the same layout and operation order, with the
+// sample kept in global memory (a.As, worked on in place) and the Householder
+// vector in dynamic LDS (2 s doubles).  n <= MAXN; each 16-lane group owns
+// MAXN / 64 columns, 4 w + q + 64 c for c = 0, 1, ...
+template <int MAXN>
 __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
+  constexpr int NS = MAXN / 64, LDR = MAXN + 1;
   extern __shared__ double vdyn[];  // [2][s]
   __shared__ double tau_s[2];
-  __shared__ double Rl[kSketchMaxN * kSketchLdr];
+  __shared__ double Rl[MAXN * LDR];
   __shared__ int bad[2];  // as in k_sketch_qr
 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int l16 = lane & 15, q = lane >> 4;
-  const int j = 4 * wave + q;  // as in k_sketch_qr
   const int n = a.n, s = a.s;
-  const bool mine = j < n;
-  double* W = a.As + (int64_t)(mine ? j : 0) * s;  // my column (padding columns never write)
 
-  for (int e = threadIdx.x; e < kSketchMaxN * kSketchLdr; e += kSketchThreads) Rl[e] = 0.0;
+  for (int e = threadIdx.x; e < MAXN * LDR; e += kSketchThreads) Rl[e] = 0.0;
   if (threadIdx.x < 2) bad[threadIdx.x] = -1;
   __syncthreads();
 
   for (int k = -1; k < n; ++k) {
     if (k >= 0 && bad[k & 1] >= 0) break;
-    if (k >= 0 && j > k && mine) {
+    if (k >= 0) {
       const int buf = k & 1;
       const double* vb = vdyn + (size_t)buf * s;
       const double tau = tau_s[buf];
-      double p = 0.0;
-      for (int r = l16; r < s; r += 16) {
-        const double v = (r >= k) ? vb[r] : 0.0;
-        p = __builtin_fma(v, mine ? W[r] : 0.0, p);
-      }
-      const double tt = tau * row16_sum(p);
-      if (mine) {
-        for (int r = l16; r < s; r += 16)
-          if (r >= k) W[r] = __builtin_fma(-tt, vb[r], W[r]);
-        if (l16 == (k & 15) && j > k) Rl[k * kSketchLdr + j] = W[k];
+#pragma unroll
+      for (int c = 0; c < NS; ++c) {
+        const int j = 4 * wave + q + 64 * c;
+        if (j > k && j < n) {  // columns j <= k are final
+          double* W = a.As + (int64_t)j * s;
+          double p = 0.0;
+          for (int r = l16; r < s; r += 16) {
+            const double v = (r >= k) ? vb[r] : 0.0;
+            p = __builtin_fma(v, W[r], p);
+          }
+          const double tt = tau * row16_sum(p);
+          for (int r = l16; r < s; r += 16)
+            if (r >= k) W[r] = __builtin_fma(-tt, vb[r], W[r]);
+          if (l16 == (k & 15)) Rl[k * LDR + j] = W[k];
+        }
       }
     }
     const int k1 = k + 1;
-    if (k1 < n && wave == (k1 >> 2)) {
-      // Column k1 is lane group k1 mod 4 of this wave; its row k1 is in lane k1 mod 16 of that group.
+    if (k1 < n && wave == ((k1 & 63) >> 2)) {
+      // Column k1 is slot k1 / 64 of lane group k1 mod 4 of this wave; its row k1
+      // is in lane k1 mod 16 of that group.
+      const int j1 = 4 * wave + q + 64 * (k1 >> 6);
+      const bool mine1 = j1 < n;
+      const double* W = a.As + (int64_t)(mine1 ? j1 : 0) * s;
       double p = 0.0;
       for (int r = l16; r < s; r += 16) {
-        const double x = (r >= k1 && mine) ? W[r] : 0.0;
+        const double x = (r >= k1 && mine1) ? W[r] : 0.0;
         p = __builtin_fma(x, x, p);
       }
       const int owner_lane = 16 * (k1 & 3) + (k1 & 15);
@@ -301,7 +321,7 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
             if (r >= k1) vb[r] = (r == k1) ? 1.0 : W[r] * d;
         if (lane == 0) {
           tau_s[k1 & 1] = tau;
-          Rl[k1 * kSketchLdr + k1] = beta;
+          Rl[k1 * LDR + k1] = beta;
         }
       }
     }
@@ -310,7 +330,7 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
   const int bad_k = bad[0] >= 0 ? bad[0] : bad[1];
   sketch_status(a, bad_k);
   if (bad_k >= 0) return;
-  sketch_finish(a, Rl);
+  sketch_finish<LDR>(a, Rl);
 }
 
 template <int RPT>
@@ -318,6 +338,9 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
   sketch_qr_body<RPT>(a);
 }
 
-__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs a) { sketch_qr_generic_body(a); }
+template <int MAXN>
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_generic(SketchArgs a) {
+  sketch_qr_generic_body<MAXN>(a);
+}
 
 }  // namespace rpq

@@ -50,8 +50,8 @@ struct CholArgs {
 };
 
 // Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
-// four waves, NMAX/16 column blocks of 16.  All matrices are staged in LDS
-// row-major with row stride kCLd.  Per block kb:
+// four waves, NMAX/16 column blocks of 16.  The matrices are row-major with a
+// padded row stride (placement below).  Per block kb:
 //   (a) wave 0 factors the 16x16 diagonal block and inverts it in the same
 //       sweep: lanes 0-15 hold the columns of the block, lanes 16-31 the rows of
 //       the identity; step k scales register k by 1/R(k,k) (lane k gets R(k,k))
@@ -64,7 +64,6 @@ struct CholArgs {
 // R = R2 R_s is a sum of MFMA block products.  Diagonal pivots use the
 // hardware reciprocal square root refined by Newton steps.
 // A non-positive or non-finite pivot gives ECHOL at its column.
-constexpr int kCLd = kCholMaxN + 1;
 
 // v_mfma_f64_16x16x4f64 operand and result positions within a 16x16 block:
 //   A(i, kk): lane l holds i = l%16, kk = l/16;  B(kk, j): kk = l/16, j = l%16;
@@ -72,71 +71,64 @@ constexpr int kCLd = kCholMaxN + 1;
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-// A operand, chunk c, of the block at (r0, c0) of row-major M.
-__device__ __forceinline__ double opA(const double* M, int r0, int c0, int c, int lane) {
-  return M[(r0 + (lane & 15)) * kCLd + c0 + 4 * c + (lane >> 4)];
+// Operands of a 16x16 block at (r0, c0) of a row-major matrix M with row stride ld.
+// A operand, chunk c.
+__device__ __forceinline__ double opA(const double* M, int ld, int r0, int c0, int c, int lane) {
+  return M[(r0 + (lane & 15)) * ld + c0 + 4 * c + (lane >> 4)];
 }
-// A operand, chunk c, of the transpose of the block at (r0, c0).
-__device__ __forceinline__ double opAT(const double* M, int r0, int c0, int c, int lane) {
-  return M[(r0 + 4 * c + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+// A operand, chunk c, of the transpose of the block.
+__device__ __forceinline__ double opAT(const double* M, int ld, int r0, int c0, int c, int lane) {
+  return M[(r0 + 4 * c + (lane >> 4)) * ld + c0 + (lane & 15)];
 }
-// B operand, chunk c, of the block at (r0, c0).
-__device__ __forceinline__ double opB(const double* M, int r0, int c0, int c, int lane) {
-  return M[(r0 + 4 * c + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+// B operand, chunk c.
+__device__ __forceinline__ double opB(const double* M, int ld, int r0, int c0, int c, int lane) {
+  return M[(r0 + 4 * c + (lane >> 4)) * ld + c0 + (lane & 15)];
 }
-__device__ __forceinline__ d4 load_d(const double* M, int r0, int c0, int lane) {
+__device__ __forceinline__ d4 load_d(const double* M, int ld, int r0, int c0, int lane) {
   d4 x;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) x[v] = M[(r0 + 4 * v + (lane >> 4)) * kCLd + c0 + (lane & 15)];
+  for (int v = 0; v < 4; ++v) x[v] = M[(r0 + 4 * v + (lane >> 4)) * ld + c0 + (lane & 15)];
   return x;
 }
-__device__ __forceinline__ void store_d(double* M, int r0, int c0, int lane, d4 x) {
+__device__ __forceinline__ void store_d(double* M, int ld, int r0, int c0, int lane, d4 x) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) M[(r0 + 4 * v + (lane >> 4)) * kCLd + c0 + (lane & 15)] = x[v];
+  for (int v = 0; v < 4; ++v) M[(r0 + 4 * v + (lane >> 4)) * ld + c0 + (lane & 15)] = x[v];
 }
 
+// NMAX <= 64: G, R2^{-1} and R_s all staged in LDS.  NMAX = 128: only G (then
+// R2) fits in LDS; R2^{-1} is built directly in the T2 output (global memory,
+// row-major, visible to the workgroup after each barrier) and R_s is read from
+// its column-major workspace copy.
 template <int NMAX>
 __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   constexpr int NB = NMAX / 16;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int E = NT * 256;
+  constexpr bool WIDE = NMAX > kCholMaxN;
+  constexpr int LD = NMAX + 1;               // LDS row stride
+  constexpr int TLD = WIDE ? NMAX : LD;      // row stride of R2^{-1}
   constexpr int PER = (E + kCholThreads - 1) / kCholThreads;  // Gram entries per thread
-  static_assert(NMAX % 16 == 0 && NMAX <= kCholMaxN, "block size");
-  __shared__ double Gs[kCholMaxN * kCLd];   // G1, then R2 (upper)
-  __shared__ double Ts[kCholMaxN * kCLd];   // R2^{-1} (upper)
-  __shared__ double Rsl[kCholMaxN * kCLd];  // R_s
+  constexpr int PCH = PER < 10 ? PER : 10;                    // entries per assembly round
+  static_assert(NMAX % 16 == 0 && (NMAX <= kCholMaxN || NMAX == 2 * kCholMaxN), "block size");
+  __shared__ double Gs[NMAX * LD];                // G1, then R2 (upper)
+  __shared__ double Tsl[WIDE ? 1 : NMAX * LD];    // R2^{-1} (upper), NMAX <= 64
+  __shared__ double Rsl[WIDE ? 1 : NMAX * LD];    // R_s, NMAX <= 64
   __shared__ int bad_s;
   if (a.info[0] != 0) return;
+  double* Ts = WIDE ? a.T2 : Tsl;
   const int n = a.n, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   if (tid == 0) bad_s = -1;
 
   // Assemble G1 (upper; identity beyond n) from the second-level partials:
-  // every load first, then the sums in ascending partial index.  Zero the
-  // lower triangles so that diagonal-block products see triangular operands.
-  {
-    // Partials are summed in ascending index; they are loaded kMaxPartial2 at a
-    // time (every load of a round in flight together).
-    double acc[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) acc[u] = 0.0;
-    for (int g0 = 0; g0 < a.G2; g0 += kMaxPartial2) {
-      double v[PER][kMaxPartial2];
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = tid + u * kCholThreads;
-#pragma unroll
-        for (int g = 0; g < kMaxPartial2; ++g)
-          v[u][g] = (e < E && g0 + g < a.G2) ? a.partial2[(int64_t)(g0 + g) * E + e] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        double t = (g0 == 0) ? v[u][0] : acc[u] + v[u][0];
-#pragma unroll
-        for (int g = 1; g < kMaxPartial2; ++g)
-          if (g0 + g < a.G2) t = t + v[u][g];
-        acc[u] = t;
-      }
-    }
+  // every load of a round first, then the sums in ascending partial index.
+  // Zero the lower triangles so that diagonal-block products see triangular
+  // operands.
+  for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
+    const int i = e / NMAX, j = e % NMAX;
+    if (WIDE) Ts[i * TLD + j] = 0.0;
+    if (i > j) Gs[i * LD + j] = 0.0;
+  }
+  if constexpr (!WIDE) {
     // R_s is column-major: consecutive threads take consecutive rows i of a
     // column.  The loads are unconditional (clamped in bounds) so that all of
     // them are in flight together; the selection happens afterwards.
@@ -152,14 +144,36 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
     for (int u = 0; u < U; ++u) {
       const int e = tid + u * kCholThreads;
       const int i = e % NMAX, j = e / NMAX;
-      Rsl[i * kCLd + j] = (i <= j && j < n) ? rv[u] : 0.0;
-      Ts[i * kCLd + j] = 0.0;
-      if (i > j) Gs[i * kCLd + j] = 0.0;
+      Rsl[i * LD + j] = (i <= j && j < n) ? rv[u] : 0.0;
+      Tsl[i * LD + j] = 0.0;
+    }
+  }
+  for (int u0 = 0; u0 < PER; u0 += PCH) {
+    double acc[PCH];
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) acc[u] = 0.0;
+    for (int g0 = 0; g0 < a.G2; g0 += kMaxPartial2) {
+      double v[PCH][kMaxPartial2];
+#pragma unroll
+      for (int u = 0; u < PCH; ++u) {
+        const int e = tid + (u0 + u) * kCholThreads;
+#pragma unroll
+        for (int g = 0; g < kMaxPartial2; ++g)
+          v[u][g] = (e < E && g0 + g < a.G2) ? a.partial2[(int64_t)(g0 + g) * E + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PCH; ++u) {
+        double t = (g0 == 0) ? v[u][0] : acc[u] + v[u][0];
+#pragma unroll
+        for (int g = 1; g < kMaxPartial2; ++g)
+          if (g0 + g < a.G2) t = t + v[u][g];
+        acc[u] = t;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * kCholThreads;
-      if (e < E) {
+    for (int u = 0; u < PCH; ++u) {
+      const int e = tid + (u0 + u) * kCholThreads;
+      if (u0 + u < PER && e < E) {
         const int tile = e >> 8, w = e & 255;
         int bi = 0, rem = tile;
 #pragma unroll
@@ -170,7 +184,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
           }
         const int bj = bi + rem;
         const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
-        if (i <= j) Gs[i * kCLd + j] = (j < n) ? acc[u] : (i == j ? 1.0 : 0.0);
+        if (i <= j) Gs[i * LD + j] = (j < n) ? acc[u] : (i == j ? 1.0 : 0.0);
       }
     }
   }
@@ -178,7 +192,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   if (a.G1_out) {
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
-      a.G1_out[e] = (i <= j) ? Gs[i * kCLd + j] : 0.0;
+      a.G1_out[e] = (i <= j) ? Gs[i * LD + j] : 0.0;
     }
   }
 
@@ -190,7 +204,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
       double g[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        g[r] = (lane < 16) ? Gs[(base + r) * kCLd + base + lane] : (lane - 16 == r ? 1.0 : 0.0);
+        g[r] = (lane < 16) ? Gs[(base + r) * LD + base + lane] : (lane - 16 == r ? 1.0 : 0.0);
       // Branch-free: a failed pivot only records its index (the first one);
       // the values computed after it are never used.
       int bad = -1;
@@ -216,10 +230,10 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
       }
       if (lane < 16) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) Gs[(base + r) * kCLd + base + lane] = (r <= lane) ? g[r] : 0.0;
+        for (int r = 0; r < 16; ++r) Gs[(base + r) * LD + base + lane] = (r <= lane) ? g[r] : 0.0;
       } else if (lane < 32) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) Ts[(base + lane - 16) * kCLd + base + c] = (c >= lane - 16) ? g[c] : 0.0;
+        for (int c = 0; c < 16; ++c) Ts[(base + lane - 16) * TLD + base + c] = (c >= lane - 16) ? g[c] : 0.0;
       }
       if (lane == 0 && bad >= 0 && bad < n) bad_s = bad;
     }
@@ -233,12 +247,13 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
     }
     if (kb + 1 < NB) {
       // (b) panel: R(kb, bj) = T(kb,kb)^T G(kb, bj).
-      if (wave < NB - 1 - kb) {
-        const int c0 = base + 16 + 16 * wave;
+      for (int pw = wave; pw < NB - 1 - kb; pw += kCholThreads / kWave) {
+        const int c0 = base + 16 + 16 * pw;
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc = mfma16(opAT(Ts, base, base, c, lane), opB(Gs, base, c0, c, lane), acc);
-        store_d(Gs, base, c0, lane, acc);
+        for (int c = 0; c < 4; ++c)
+          acc = mfma16(opAT(Ts, TLD, base, base, c, lane), opB(Gs, LD, base, c0, c, lane), acc);
+        store_d(Gs, LD, base, c0, lane, acc);
       }
       __syncthreads();
       // (c) trailing update of the blocks (bi, bj), kb < bi <= bj.
@@ -248,11 +263,11 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
 #pragma unroll
         for (int bj = bi; bj < NB; ++bj) {
           if (q % 4 == wave) {
-            d4 acc = load_d(Gs, 16 * bi, 16 * bj, lane);
+            d4 acc = load_d(Gs, LD, 16 * bi, 16 * bj, lane);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-              acc = mfma16(-opAT(Gs, base, 16 * bi, c, lane), opB(Gs, base, 16 * bj, c, lane), acc);
-            store_d(Gs, 16 * bi, 16 * bj, lane, acc);
+              acc = mfma16(-opAT(Gs, LD, base, 16 * bi, c, lane), opB(Gs, LD, base, 16 * bj, c, lane), acc);
+            store_d(Gs, LD, 16 * bi, 16 * bj, lane, acc);
           }
           ++q;
         }
@@ -263,16 +278,17 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   // Off-diagonal blocks of T = R2^{-1}, by increasing distance from the diagonal.
 #pragma unroll
   for (int dist = 1; dist < NB; ++dist) {
-    const int bi = wave, bj = wave + dist;
-    if (bj < NB) {
+    for (int bi = wave; bi + dist < NB; bi += kCholThreads / kWave) {
+      const int bj = bi + dist;
       d4 p = {0.0, 0.0, 0.0, 0.0};
       for (int l = bi + 1; l <= bj; ++l)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) p = mfma16(opA(Gs, 16 * bi, 16 * l, c, lane), opB(Ts, 16 * l, 16 * bj, c, lane), p);
+        for (int c = 0; c < 4; ++c)
+          p = mfma16(opA(Gs, LD, 16 * bi, 16 * l, c, lane), opB(Ts, TLD, 16 * l, 16 * bj, c, lane), p);
       d4 t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) t = mfma16(-opA(Ts, 16 * bi, 16 * bi, c, lane), p[c], t);
-      store_d(Ts, 16 * bi, 16 * bj, lane, t);
+      for (int c = 0; c < 4; ++c) t = mfma16(-opA(Ts, TLD, 16 * bi, 16 * bi, c, lane), p[c], t);
+      store_d(Ts, TLD, 16 * bi, 16 * bj, lane, t);
     }
     __syncthreads();
   }
@@ -280,13 +296,19 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   if (a.R2_out) {
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
-      a.R2_out[e] = (i <= j) ? Gs[i * kCLd + j] : 0.0;
+      a.R2_out[e] = (i <= j) ? Gs[i * LD + j] : 0.0;
     }
   }
   // T2 for pass B: NMAX x NMAX row-major, zero outside the n x n upper triangle.
-  for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
-    const int i = e / NMAX, j = e % NMAX;
-    a.T2[e] = (j >= i && j < n) ? Ts[i * kCLd + j] : 0.0;
+  if constexpr (!WIDE) {
+    for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
+      const int i = e / NMAX, j = e % NMAX;
+      a.T2[e] = (j >= i && j < n) ? Tsl[i * LD + j] : 0.0;
+    }
+  } else {
+    // Beyond n, R2 is the identity, so its inverse holds exact zeros there
+    // except for the unit diagonal, cleared here.
+    if (tid >= n && tid < NMAX) a.T2[tid * NMAX + tid] = 0.0;
   }
   // Line 8: R = R2 R_s, upper block tiles on MFMA; blocks below the diagonal are zero.
   {
@@ -299,7 +321,16 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
           d4 acc = {0.0, 0.0, 0.0, 0.0};
           for (int l = bi; l <= bj; ++l)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc = mfma16(opA(Gs, 16 * bi, 16 * l, c, lane), opB(Rsl, 16 * l, 16 * bj, c, lane), acc);
+            for (int c = 0; c < 4; ++c) {
+              double b;
+              if constexpr (WIDE) {
+                const int r = 16 * l + 4 * c + (lane >> 4), cc = 16 * bj + (lane & 15);
+                b = (r < n && cc < n) ? a.Rs[r + (int64_t)cc * n] : 0.0;
+              } else {
+                b = opB(Rsl, LD, 16 * l, 16 * bj, c, lane);
+              }
+              acc = mfma16(opA(Gs, LD, 16 * bi, 16 * l, c, lane), b, acc);
+            }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = 16 * bi + 4 * v + (lane >> 4), j = 16 * bj + (lane & 15);

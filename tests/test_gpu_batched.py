@@ -49,6 +49,7 @@ MIXED = [
     (2500, 48, 144, 1e14), (10000, 50, 150, 1e8), (7777, 64, 192, 1e15), (128, 64, 640, 1e3),
     (60000, 20, 20, 1e5), (130, 20, 40, 1e5), (20000, 64, 520, 1e12), (3000, 5, 1536, 1e9),
     (65, 33, 99, 1e2), (150000, 64, 192, 1e8), (70000, 17, 51, 1e13),
+    (5001, 96, 288, 1e12), (20000, 128, 384, 1e14), (300, 65, 195, 1e4), (2000, 128, 1536, 1e6),
 ]
 
 
@@ -161,9 +162,9 @@ def test_batched_argument_errors():
     A = dev(gen_usv(1000, 8, 10.0, 1))
     Q = rq().colmajor_empty(1000, 8, "cuda")
     R = rq().colmajor_empty(8, 8, "cuda")
-    big = rq().colmajor_empty(1000, 65, "cuda")
-    Qb = rq().colmajor_empty(1000, 65, "cuda")
-    Rb = rq().colmajor_empty(65, 65, "cuda")
+    big = rq().colmajor_empty(1000, 129, "cuda")
+    Qb = rq().colmajor_empty(1000, 129, "cuda")
+    Rb = rq().colmajor_empty(129, 129, "cuda")
     I64 = ctypes.c_int64 * 2
     P = ctypes.c_void_p * 2
 
@@ -173,14 +174,14 @@ def test_batched_argument_errors():
         rc = lib.rpcholqr_batched_plan_create(
             2, I64(1000, 1000), I64(8, n1), I64(24, s1), (ctypes.c_uint64 * 2)(1, 2),
             P(A.data_ptr(), A1.data_ptr()), I64(1000, 1000), P(Q.data_ptr(), Qb.data_ptr()), I64(1000, ldq1),
-            P(R.data_ptr(), Rb.data_ptr()), I64(8, 65), 0, ctypes.byref(h), ctypes.byref(bad))
+            P(R.data_ptr(), Rb.data_ptr()), I64(8, 129), 0, ctypes.byref(h), ctypes.byref(bad))
         if rc == 0:
             lib.rpcholqr_batched_plan_destroy(h)
         return rc, bad.value
 
     announce("batched argument errors")
     assert create() == (0, -1)
-    assert create(n1=65, A1=big, s1=200) == (-4, 1)      # n beyond the supported maximum
+    assert create(n1=129, A1=big, s1=400) == (-4, 1)     # n beyond the supported maximum
     assert create(ldq1=999) == (-1, 1)                    # ldq < m
     assert create(s1=4) == (-1, 1)                        # s < n
     assert lib.rpcholqr_batched_execute(None, None, None) == -1

@@ -96,6 +96,20 @@ CASES = [
     (65, 33, 99, 1e2, 16),
 ]
 
+# 64 < n <= 128: the two-half row solve (A1 bit-exact across the half boundary),
+# the separate Gram pass and the LDS-resident pass B; ragged column counts, s = n,
+# s = 3n, the largest s the generic sketch kernel takes, a single row-panel group.
+WIDE_CASES = [
+    (3000, 65, 195, 1e8, 20),
+    (5001, 96, 288, 1e12, 21),
+    (4099, 100, 300, 1e15, 22),
+    (20000, 128, 384, 1e14, 23),
+    (100000, 96, 96, 1e5, 24),      # s = n (m large, so the sample has no repeated rows)
+    (2000, 128, 1536, 1e6, 25),     # largest s
+    (200, 70, 210, 1e3, 26),        # a single row-panel group, m < 4 * 64
+    (100003, 112, 336, 1e10, 27),
+]
+
 
 @pytest.mark.parametrize("m,n,s,kappa,seed", CASES)
 def test_parity_small(m, n, s, kappa, seed):
@@ -103,6 +117,14 @@ def test_parity_small(m, n, s, kappa, seed):
     _, _, orth, res = check_case(A_h, s, seed)
     # Section 5.1: orth <= 1e-12 and residual below 1e-15 with c = 3n samples; with
     # fewer samples kappa(A1) grows and so does the orthogonality error (Section 5.2).
+    assert orth < (1e-12 if s >= 2 * n else 1e-10)
+    assert res < 1e-15
+
+
+@pytest.mark.parametrize("m,n,s,kappa,seed", WIDE_CASES)
+def test_parity_wide(m, n, s, kappa, seed):
+    A_h = gen_usv(m, n, kappa, 100 + seed)
+    _, _, orth, res = check_case(A_h, s, seed)
     assert orth < (1e-12 if s >= 2 * n else 1e-10)
     assert res < 1e-15
 
@@ -116,11 +138,12 @@ def test_deterministic_bits():
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
-@pytest.mark.parametrize("pad,off", [(13, 0), (14, 0), (14, 1)])
-def test_leading_dimensions(pad, off):
-    # Even lda with a 16-byte aligned A takes the LDS-staged pass A; an odd lda or
-    # an A that starts 8 bytes into an allocation takes the register-load kernel.
-    m, n, s = 3001, 24, 72
+@pytest.mark.parametrize("pad,off,n", [(13, 0, 24), (14, 0, 24), (14, 1, 24), (13, 0, 100), (14, 1, 100)])
+def test_leading_dimensions(pad, off, n):
+    # Odd and even leading dimensions, and an A that starts 8 bytes into its
+    # allocation, for a 64-column class and the 128-column class.
+    m = 3001
+    s = 3 * n
     A_h = gen_usv(m, n, 1e6, 4)
     announce(f"padded leading dimensions pad={pad} off={off}")
     big = torch.full((n, m + pad), float("nan"), dtype=torch.float64, device="cuda").t()
@@ -133,27 +156,29 @@ def test_leading_dimensions(pad, off):
     assert metrics.rel_fro(host(Q), ref.Q) < TOL and metrics.rel_fro(host(R), ref.R) < TOL
 
 
-def test_esketch_zero_column():
-    A_h = gen_usv(2000, 12, 1e3, 1)
-    A_h[:, 7] = 0.0
-    announce("ESKETCH zero column")
+@pytest.mark.parametrize("n,col", [(12, 7), (100, 90)])
+def test_esketch_zero_column(n, col):
+    A_h = gen_usv(2000, n, 1e3, 1)
+    A_h[:, col] = 0.0
+    announce(f"ESKETCH zero column {col} of {n}")
     with pytest.raises(rq().RpCholQRError) as e:
-        rq().factor(dev(A_h), 36, 0)
-    assert e.value.code == 1 and e.value.index == 7
-    assert oracle.rpcholqr(A_h, 36, 0).index == 7
+        rq().factor(dev(A_h), 3 * n, 0)
+    assert e.value.code == 1 and e.value.index == col
+    assert oracle.rpcholqr(A_h, 3 * n, 0).index == col
 
 
-def test_echol_nonfinite_unsampled_row():
-    m, n, s = 2000, 12, 36
+@pytest.mark.parametrize("n,col", [(12, 3), (80, 70)])
+def test_echol_nonfinite_unsampled_row(n, col):
+    m, s = 2000, 3 * n
     A_h = gen_usv(m, n, 1e3, 2)
     missed = sorted(set(range(m)) - set(oracle.sample_indices(m, s, 0).tolist()))[5]
-    A_h[missed, 3] = np.nan
-    announce("ECHOL NaN row")
+    A_h[missed, col] = np.nan
+    announce(f"ECHOL NaN row, column {col} of {n}")
     with pytest.raises(rq().RpCholQRError) as e:
         rq().factor(dev(A_h), s, 0)
     ref = oracle.rpcholqr(A_h, s, 0)
     assert ref.status == oracle.ECHOL
-    assert e.value.code == 2 and e.value.index == ref.index == 3
+    assert e.value.code == 2 and e.value.index == ref.index == col
 
 
 def test_esketch_inf_in_sample():
