@@ -32,6 +32,15 @@ __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr(const SketchArgs*
   sketch_qr_body<RPT>(a);
 }
 
+template <int RPT>
+__global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr_wide(const SketchArgs* __restrict__ args,
+                                                                    const int32_t* __restrict__ probs, int32_t* info) {
+  const int p = probs[blockIdx.x];
+  SketchArgs a = args[p];
+  a.info = info + 2 * p;
+  sketch_qr_body<RPT, true>(a);
+}
+
 template <int MAXN>
 __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr_generic(const SketchArgs* __restrict__ args,
                                                                        const int32_t* __restrict__ probs,

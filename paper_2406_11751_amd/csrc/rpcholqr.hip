@@ -72,7 +72,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
   p->G2 = direct_partials ? p->PA : (p->PA + kReduceChunk - 1) / kReduceChunk;
   const int64_t rows = (s + 15) / 16;
   p->rpt = rows <= 4 ? 4 : rows <= 8 ? 8 : rows <= 12 ? 12 : rows <= 16 ? 16 : rows <= 24 ? 24 : 0;
-  if (p->nmax == kWideN) p->rpt = 0;  // the register sketch kernels hold 64 columns
+  if (p->nmax == kWideN && p->rpt > 0 && p->rpt < 8) p->rpt = 8;  // rows 64..127 live in slots 4..7
   if (p->rpt == 0 && s > kMaxSketchRows) return false;
   // nmax <= 64: one packed triangle; nmax = 128: R11, R22 packed and R12 64 x 64,
   // 2 * 2080 + 4096 = 128 * 129 / 2 doubles as well.
@@ -107,6 +107,15 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
 
 void launch_sketch(const Plan& p, const SketchArgs& a, hipStream_t st) {
   const dim3 blk(kSketchThreads);
+  if (p.nmax == kWideN && p.rpt > 0) {
+    switch (p.rpt) {
+      case 8: hipLaunchKernelGGL((k_sketch_qr_wide<8>), dim3(1), blk, 0, st, a); break;
+      case 12: hipLaunchKernelGGL((k_sketch_qr_wide<12>), dim3(1), blk, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((k_sketch_qr_wide<16>), dim3(1), blk, 0, st, a); break;
+      default: hipLaunchKernelGGL((k_sketch_qr_wide<24>), dim3(1), blk, 0, st, a); break;
+    }
+    return;
+  }
   switch (p.rpt) {
     case 4: hipLaunchKernelGGL((k_sketch_qr<4>), dim3(1), blk, 0, st, a); break;
     case 8: hipLaunchKernelGGL((k_sketch_qr<8>), dim3(1), blk, 0, st, a); break;
@@ -389,9 +398,13 @@ constexpr int64_t kBatchPartialsMax = 64;   // pass-A workgroups (Gram partials)
 constexpr int64_t kBatchPgroupsPerWG = 8;   // target panel groups per pass-A workgroup
 constexpr int64_t kBatchBIters = 16;        // target 4-block iterations per pass-B workgroup
 
-// Sketch class of a problem: the register kernel's RPT, 0 for the generic
-// kernel with n <= 64, -1 for the generic kernel with n <= 128.
-int sketch_key(const Plan& p) { return p.nmax == kWideN ? -1 : p.rpt; }
+// Sketch class of a problem: the register kernel's RPT (plus 100 for the wide
+// register kernel), 0 for the generic kernel with n <= 64, -1 for the generic
+// kernel with n <= 128.
+int sketch_key(const Plan& p) {
+  if (p.nmax == kWideN) return p.rpt > 0 ? 100 + p.rpt : -1;
+  return p.rpt;
+}
 
 // 16-row blocks of pass B per workgroup and target iteration count.
 int64_t pass_b_items(int nmax, int64_t m) {
@@ -639,6 +652,10 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 12: hipLaunchKernelGGL((kb_sketch_qr<12>), g, blk, 0, st, sk, probs, inf); break;
       case 16: hipLaunchKernelGGL((kb_sketch_qr<16>), g, blk, 0, st, sk, probs, inf); break;
       case 24: hipLaunchKernelGGL((kb_sketch_qr<24>), g, blk, 0, st, sk, probs, inf); break;
+      case 108: hipLaunchKernelGGL((kb_sketch_qr_wide<8>), g, blk, 0, st, sk, probs, inf); break;
+      case 112: hipLaunchKernelGGL((kb_sketch_qr_wide<12>), g, blk, 0, st, sk, probs, inf); break;
+      case 116: hipLaunchKernelGGL((kb_sketch_qr_wide<16>), g, blk, 0, st, sk, probs, inf); break;
+      case 124: hipLaunchKernelGGL((kb_sketch_qr_wide<24>), g, blk, 0, st, sk, probs, inf); break;
       case 0:
         hipLaunchKernelGGL((kb_sketch_qr_generic<64>), g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs, inf);
         break;

@@ -141,11 +141,22 @@ __device__ __forceinline__ void sketch_status(const SketchArgs& a, int bad_k) {
 // step k every wave applies reflector k to its columns that are not final yet,
 // and the wave owning column k+1 then forms reflector k+1 from the freshly
 // updated column into the other LDS buffer.
-template <int RPT>
+//
+// WIDE (64 < n <= 128): the group also owns column j + 64.  Phase 1 runs steps
+// 0..63 on columns 0..63 and keeps each reflector v_k in place of sample column
+// k (no longer needed) and tau_k in LDS; phase 2 applies reflectors 0..63 to
+// columns 64..127, each group its own column with no barriers; phase 3 runs
+// steps 64..127 on columns 64..127.  Every column receives the same reflectors
+// in the same order with the same arithmetic as in the unblocked sweep, so R is
+// the same to the bit.
+template <int RPT, bool WIDE = false>
 __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
+  constexpr int MAXN = WIDE ? 2 * kSketchMaxN : kSketchMaxN, LDR = MAXN + 1;
+  static_assert(!WIDE || RPT >= 8, "rows 64..127 need slots 4..7");
   __shared__ double vbuf[2][16 * RPT];
   __shared__ double tau_s[2];
-  __shared__ double Rl[kSketchMaxN * kSketchLdr];
+  __shared__ double tau_all[WIDE ? kSketchMaxN : 1];
+  __shared__ double Rl[MAXN * LDR];
   // bad[k & 1] = k when reflector k has a zero or non-finite norm.  Written by
   // the wave forming reflector k during step k-1, read by all after the barrier
   // that ends step k-1: never read and written in the same step.
@@ -155,15 +166,19 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
   const int l16 = lane & 15, q = lane >> 4;
   const int j = 4 * wave + q;  // my column: each wave owns four consecutive columns
   const int n = a.n, s = a.s;
+  int jc = j;  // the column currently in W (j, then j + 64 when WIDE)
 
-  for (int e = threadIdx.x; e < kSketchMaxN * kSketchLdr; e += kSketchThreads) Rl[e] = 0.0;
+  for (int e = threadIdx.x; e < MAXN * LDR; e += kSketchThreads) Rl[e] = 0.0;
   if (threadIdx.x < 2) bad[threadIdx.x] = -1;
   double W[RPT];
+  auto load_column = [&]() __attribute__((always_inline)) {
 #pragma unroll
-  for (int t = 0; t < RPT; ++t) {
-    const int r = l16 + 16 * t;
-    W[t] = (j < n && r < s) ? a.As[r + (int64_t)j * s] : 0.0;
-  }
+    for (int t = 0; t < RPT; ++t) {
+      const int r = l16 + 16 * t;
+      W[t] = (jc < n && r < s) ? a.As[r + (int64_t)jc * s] : 0.0;
+    }
+  };
+  load_column();
   __syncthreads();
 
   // Reflector k from my column (this wave owns column k, in lane group k mod 4;
@@ -194,12 +209,17 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int r = l16 + 16 * t;
-        if (r >= k && r < s) vbuf[buf][r] = (r == k) ? 1.0 : W[t] * d;
+        if (r >= k && r < s) {
+          const double v = (r == k) ? 1.0 : W[t] * d;
+          vbuf[buf][r] = v;
+          if (WIDE && k < kSketchMaxN) a.As[r + (int64_t)k * s] = v;
+        }
       }
     }
     if (lane == 0) {
       tau_s[buf] = tau;
-      Rl[k * kSketchLdr + k] = beta;
+      if (WIDE && k < kSketchMaxN) tau_all[k] = tau;
+      Rl[k * LDR + k] = beta;
     }
   };
 
@@ -222,32 +242,68 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     const double tt = tau * row16_sum(p);
 #pragma unroll
     for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vk[t], W[t]);
-    if (l16 == (k & 15) && j > k && j < n) Rl[k * kSketchLdr + j] = W[KB];
+    if (l16 == (k & 15) && jc > k && jc < n) Rl[k * LDR + jc] = W[KB];
   };
 
-  if (wave == 0) reflector(std::integral_constant<int, 0>{}, 0);
-  __syncthreads();
-  static_for<4>([&](auto kbI) __attribute__((always_inline)) {
-    constexpr int KB = decltype(kbI)::value;
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * KB + kk;
-      if (k >= n || bad[k & 1] >= 0) break;
-      // Columns j <= k are final (reflector k would only add exact zeros to
-      // them); waves whose four columns are all final idle until the barrier.
-      if (j > k && j < n) apply(std::integral_constant<int, KB>{}, k);
-      if (k + 1 < n && wave == ((k + 1) >> 2)) {
-        if (kk < 15)
-          reflector(std::integral_constant<int, KB>{}, k + 1);
-        else if constexpr (KB < 3)
-          reflector(std::integral_constant<int, KB + 1>{}, k + 1);
+  // Steps 16 KB0 .. 16 KB0 + 63 of the sweep (the columns of W are jc).
+  auto sweep = [&](auto kb0) __attribute__((always_inline)) {
+    constexpr int KB0 = decltype(kb0)::value;
+    if (wave == 0) reflector(std::integral_constant<int, KB0>{}, 16 * KB0);
+    __syncthreads();
+    static_for<4>([&](auto kbI) __attribute__((always_inline)) {
+      constexpr int KB = KB0 + decltype(kbI)::value;
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = 16 * KB + kk;
+        if (k >= n || bad[k & 1] >= 0) break;
+        // Columns jc <= k are final (reflector k would only add exact zeros to
+        // them); waves whose four columns are all final idle until the barrier.
+        if (jc > k && jc < n) apply(std::integral_constant<int, KB>{}, k);
+        if (k + 1 < n && wave == (((k + 1) & 63) >> 2)) {
+          if (kk < 15)
+            reflector(std::integral_constant<int, KB>{}, k + 1);
+          else if constexpr (KB < KB0 + 3)
+            reflector(std::integral_constant<int, KB + 1>{}, k + 1);
+        }
+        __syncthreads();
       }
+    });
+  };
+
+  sweep(std::integral_constant<int, 0>{});
+  if constexpr (WIDE) {
+    if (n > kSketchMaxN && bad[0] < 0 && bad[1] < 0) {
+      // Phase 2: reflectors 0..63 (kept in sample columns 0..63) on column j + 64.
+      jc = j + kSketchMaxN;
+      load_column();
+      static_for<4>([&](auto kbI) __attribute__((always_inline)) {
+        constexpr int KB = decltype(kbI)::value;
+        for (int kk = 0; kk < 16; ++kk) {
+          const int k = 16 * KB + kk;
+          const double tau = tau_all[k];
+          double vk[RPT];
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            const int r = l16 + 16 * t;
+            vk[t] = (r >= k && r < s) ? a.As[r + (int64_t)k * s] : 0.0;
+          }
+          double p = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) p = __builtin_fma(vk[t], W[t], p);
+          const double tt = tau * row16_sum(p);
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vk[t], W[t]);
+          if (l16 == (k & 15) && jc < n) Rl[k * LDR + jc] = W[KB];
+        }
+      });
       __syncthreads();
+      // Phase 3: steps 64..127.
+      sweep(std::integral_constant<int, 4>{});
     }
-  });
+  }
   const int bad_k = bad[0] >= 0 ? bad[0] : bad[1];
   sketch_status(a, bad_k);
   if (bad_k >= 0) return;
-  sketch_finish<kSketchLdr>(a, Rl);
+  sketch_finish<LDR>(a, Rl);
 }
 
 // Line 3 for large s or n > 64: the same layout and operation order, with the
@@ -336,6 +392,11 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
 template <int RPT>
 __global__ __launch_bounds__(kSketchThreads) void k_sketch_qr(SketchArgs a) {
   sketch_qr_body<RPT>(a);
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kSketchThreads) void k_sketch_qr_wide(SketchArgs a) {
+  sketch_qr_body<RPT, true>(a);
 }
 
 template <int MAXN>

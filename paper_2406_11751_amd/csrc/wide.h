@@ -70,6 +70,53 @@ __device__ __forceinline__ void update_row64(double (&t)[kWH], P B, const double
   }
 }
 
+// The same update with B (row-major 64 x 64) in LDS: B arrives as wave-uniform
+// 16-byte LDS reads (every lane reads the same address) in groups of eight
+// values, RING groups in flight; LDS reads of a wave return in issue order, so
+// the wait for a group leaves the later groups outstanding.  The fma order per
+// element is that of update_row64.
+template <int RING>
+__device__ __forceinline__ void update_row64_lds(double (&t)[kWH], const double* Bl, const double* X, int64_t ldx,
+                                                 int lane, bool valid) {
+  constexpr int G = 8, NG = kWH * kWH / G, D = 8;
+  static_assert(kWH % G == 0 && NG >= RING, "groups");
+  auto xload = [&](int k) -> double {
+    int64_t off = (int64_t)k * ldx;
+    asm volatile("" : "+s"(off));
+    return valid ? (X + off)[lane] : 0.0;
+  };
+  double xr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) xr[d] = xload(d);
+  double buf[RING][G];
+#pragma unroll
+  for (int r = 0; r < RING; ++r)
+#pragma unroll
+    for (int i = 0; i < G; ++i) buf[r][i] = Bl[r * G + i];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int slot = g % RING;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int p = g * G + i;
+      const int k = p / kWH, j = p % kWH;
+      t[j] = __builtin_fma(-xr[k % D], buf[slot][i], t[j]);
+      if (j == kWH - 1 && k + D < kWH) xr[k % D] = xload(k + D);
+    }
+    // The group's results are pinned here and the memory clobber keeps the LDS
+    // reads of later groups below this point: otherwise the optimizer sinks the
+    // fmas and hoists the reads, and all 4096 values of B are live at once.
+#pragma unroll
+    for (int i = 0; i < G; ++i) asm volatile("" : "+v"(t[(g * G + i) % kWH]));
+    asm volatile("" ::: "memory");
+    if (g + RING < NG) {
+#pragma unroll
+      for (int i = 0; i < G; ++i) buf[slot][i] = Bl[(g + RING) * G + i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Stores columns 0 .. ncols-1 of this lane's half row at W + r0 (ld ldw).
 __device__ __forceinline__ void store_half(double* W, int64_t ldw, const double (&t)[kWH], int64_t r0, int lane,
                                            bool valid, int ncols) {
@@ -85,7 +132,12 @@ __device__ __forceinline__ void store_half(double* W, int64_t ldw, const double 
 // HALF 0: first 64 columns; HALF 1: the remaining n - 64 columns.
 template <int HALF>
 __device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk) {
+  __shared__ __attribute__((aligned(16))) double r12s[HALF == 1 ? kWH * kWH : 2];
   if (a.info[0] != 0) return;
+  if constexpr (HALF == 1) {
+    for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads) r12s[e] = a.tri_s[2 * kWideTri + e];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int64_t panels = (a.m + kWave - 1) / kWave;
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
@@ -97,8 +149,7 @@ __device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk
     load_row<kWH>(t, a.A + (int64_t)HALF * kWH * a.lda, r0, a.lda, ncols, lane, valid);
     pin_values(t);
     if constexpr (HALF == 1) {
-      update_row64<kTriGroup / 2, kTriSync * 2>(t, opaque(as_const(a.tri_s + 2 * kWideTri)), a.W + r0, a.ldw, lane,
-                                        valid);
+      update_row64_lds<4>(t, opaque(static_cast<const double*>(r12s)), a.W + r0, a.ldw, lane, valid);
       pin_values(t);
       trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s + kWideTri)));
     } else {
@@ -131,14 +182,31 @@ struct WideTiles {
 constexpr int kGramRows = 32;
 constexpr int kGramLd = 2 * kWH + 1;
 
-// Partial Gram of the m x n matrix a.W (n <= 128) over the workgroup's 32-row
-// blocks, written to a.partials[bid][tile * 256 + i * 16 + j].
-__device__ __forceinline__ void gramW_body(const PassAArgs& a, int bid, int nblk) {
+// Tiles W, W + 4, ... of one 4-row chunk (operand rows of the LDS block at
+// xq): the tile set of each wave is fixed at compile time, so every operand and
+// accumulator index is static.
+template <int W>
+__device__ __forceinline__ void gram_chunk(d4 (&acc)[kWideNT / kPassWaves], const double* xq, int cq) {
   constexpr WideTiles map{};
+  constexpr int MT = kWideNT / kPassWaves;
+  double v[kWideNB];
+#pragma unroll
+  for (int b = 0; b < kWideNB; ++b) v[b] = xq[16 * b + cq];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[map.bi[W + kPassWaves * i]], v[map.bj[W + kPassWaves * i]],
+                                                  acc[i], 0, 0, 0);
+  }
+}
+
+// Partial Gram of the m x n matrix a.W (n <= 128) over the workgroup's 32-row
+// blocks, written to a.partials[bid][tile * 256 + i * 16 + j].  Wave W owns
+// tiles W, W + 4, ...; each wave runs its own instance of the block loop (same
+// barriers), so that its accumulators keep one register assignment.
+template <int W>
+__device__ __forceinline__ void gram_loop(const PassAArgs& a, int bid, int nblk, double* xs) {
   constexpr int MT = kWideNT / kPassWaves;  // tiles per wave
-  __shared__ double xs[kGramRows * kGramLd];
-  if (a.info[0] != 0) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1);
   const int rq = lane >> 4, cq = lane & 15;
   d4 acc[MT];
 #pragma unroll
@@ -155,24 +223,26 @@ __device__ __forceinline__ void gramW_body(const PassAArgs& a, int bid, int nblk
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kGramRows / 4; ++q) {
-      double v[kWideNB];
-#pragma unroll
-      for (int b = 0; b < kWideNB; ++b) v[b] = xs[(4 * q + rq) * kGramLd + 16 * b + cq];
-#pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        const int tile = wave + kPassWaves * i;
-        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[map.bi[tile]], v[map.bj[tile]], acc[i], 0, 0, 0);
-      }
-    }
+    for (int q = 0; q < kGramRows / 4; ++q) gram_chunk<W>(acc, xs + (4 * q + rq) * kGramLd, cq);
   }
   // Result element (i, j) of a tile sits in lane j + 16 (i mod 4), register i / 4.
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
-    const int tile = wave + kPassWaves * i;
+    const int tile = W + kPassWaves * i;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       a.partials[(int64_t)bid * kWideE + tile * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[i][v];
+  }
+}
+
+__device__ __forceinline__ void gramW_body(const PassAArgs& a, int bid, int nblk) {
+  __shared__ double xs[kGramRows * kGramLd];
+  if (a.info[0] != 0) return;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: gram_loop<0>(a, bid, nblk, xs); break;
+    case 1: gram_loop<1>(a, bid, nblk, xs); break;
+    case 2: gram_loop<2>(a, bid, nblk, xs); break;
+    default: gram_loop<3>(a, bid, nblk, xs); break;
   }
 }
 
