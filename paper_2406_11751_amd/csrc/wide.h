@@ -149,7 +149,11 @@ __device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk
     load_row<kWH>(t, a.A + (int64_t)HALF * kWH * a.lda, r0, a.lda, ncols, lane, valid);
     pin_values(t);
     if constexpr (HALF == 1) {
-      update_row64_lds<4>(t, opaque(static_cast<const double*>(r12s)), a.W + r0, a.ldw, lane, valid);
+      // A per-lane (all equal) base: the LDS reads then take their offsets as
+      // immediates instead of one address register each.
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      update_row64_lds<4>(t, static_cast<const double*>(r12s) + 2 * z, a.W + r0, a.ldw, lane, valid);
       pin_values(t);
       trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s + kWideTri)));
     } else {
@@ -211,17 +215,32 @@ __device__ __forceinline__ void gram_loop(const PassAArgs& a, int bid, int nblk,
   d4 acc[MT];
 #pragma unroll
   for (int i = 0; i < MT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  // The next block's values are loaded into registers while the current block
+  // is contracted from LDS.
+  constexpr int U = kGramRows * 2 * kWH / kPassThreads;
   const int64_t blocks = (a.m + kGramRows - 1) / kGramRows;
-  for (int64_t blk = bid; blk < blocks; blk += nblk) {
+  double nx[U];
+  auto fetch = [&](int64_t blk) __attribute__((always_inline)) {
     const int64_t r0 = blk * kGramRows;
-    __syncthreads();
+    int n = a.n;
+    asm volatile("" : "+s"(n));
 #pragma unroll
-    for (int u = 0; u < kGramRows * 2 * kWH / kPassThreads; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = threadIdx.x + u * kPassThreads;
       const int r = e % kGramRows, c = e / kGramRows;
-      xs[r * kGramLd + c] = (r0 + r < a.m && c < a.n) ? a.W[r0 + r + (int64_t)c * a.ldw] : 0.0;
+      nx[u] = (blk < blocks && r0 + r < a.m && c < n) ? a.W[r0 + r + (int64_t)c * a.ldw] : 0.0;
+    }
+  };
+  fetch(bid);
+  for (int64_t blk = bid; blk < blocks; blk += nblk) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kPassThreads;
+      xs[(e % kGramRows) * kGramLd + e / kGramRows] = nx[u];
     }
     __syncthreads();
+    fetch(blk + nblk);
 #pragma unroll
     for (int q = 0; q < kGramRows / 4; ++q) gram_chunk<W>(acc, xs + (4 * q + rq) * kGramLd, cq);
   }
