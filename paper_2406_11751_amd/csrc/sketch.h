@@ -206,14 +206,14 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     const double d = 1.0 / (alpha - beta);
     const double tau = (beta - alpha) / beta;
     if (q == (k & 3)) {
+      // Every slot is written (zero outside rows k .. s-1), so that the
+      // reflector's readers need no row mask.
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int r = l16 + 16 * t;
-        if (r >= k && r < s) {
-          const double v = (r == k) ? 1.0 : W[t] * d;
-          vbuf[buf][r] = v;
-          if (WIDE && k < kSketchMaxN) a.As[r + (int64_t)k * s] = v;
-        }
+        const double v = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+        vbuf[buf][r] = v;
+        if (WIDE && k < kSketchMaxN && r < s) a.As[r + (int64_t)k * s] = v;
       }
     }
     if (lane == 0) {
@@ -232,10 +232,7 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     const double tau = tau_s[buf];
     double vk[RPT];
 #pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int r = l16 + 16 * t;
-      vk[t] = (r >= k && r < s) ? vbuf[buf][r] : 0.0;
-    }
+    for (int t = 0; t < RPT; ++t) vk[t] = vbuf[buf][l16 + 16 * t];  // zero outside rows k .. s-1
     double p = 0.0;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) p = __builtin_fma(vk[t], W[t], p);

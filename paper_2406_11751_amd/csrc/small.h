@@ -128,24 +128,18 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
     if (WIDE) Ts[i * TLD + j] = 0.0;
     if (i > j) Gs[i * LD + j] = 0.0;
   }
+  // R_s is column-major: consecutive threads take consecutive rows i of a
+  // column.  The loads are unconditional (clamped in bounds) and are issued
+  // before the partial Gram loads below, so that both sets are in flight
+  // together; they are placed in LDS after the assembly.
+  constexpr int U = WIDE ? 1 : NMAX * NMAX / kCholThreads;
+  double rv[U];
   if constexpr (!WIDE) {
-    // R_s is column-major: consecutive threads take consecutive rows i of a
-    // column.  The loads are unconditional (clamped in bounds) so that all of
-    // them are in flight together; the selection happens afterwards.
-    constexpr int U = NMAX * NMAX / kCholThreads;
-    double rv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = tid + u * kCholThreads;
       const int i = min(e % NMAX, n - 1), j = min(e / NMAX, n - 1);
       rv[u] = a.Rs[i + j * n];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = tid + u * kCholThreads;
-      const int i = e % NMAX, j = e / NMAX;
-      Rsl[i * LD + j] = (i <= j && j < n) ? rv[u] : 0.0;
-      Tsl[i * LD + j] = 0.0;
     }
   }
   for (int u0 = 0; u0 < PER; u0 += PCH) {
@@ -186,6 +180,15 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
         const int i = 16 * bi + (w >> 4), j = 16 * bj + (w & 15);
         if (i <= j) Gs[i * LD + j] = (j < n) ? acc[u] : (i == j ? 1.0 : 0.0);
       }
+    }
+  }
+  if constexpr (!WIDE) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + u * kCholThreads;
+      const int i = e % NMAX, j = e / NMAX;
+      Rsl[i * LD + j] = (i <= j && j < n) ? rv[u] : 0.0;
+      Tsl[i * LD + j] = 0.0;
     }
   }
   __syncthreads();
