@@ -214,9 +214,14 @@ def main():
     #   pass A: read A (8mn bytes); A1 = A R_s^{-1} (m n^2 flops) and G1 = A1^T A1 upper (m n (n+1) flops);
     #   pass B: read A1, write Q (16mn bytes); Q = A1 R2^{-1} (m n^2 flops).
     # Storing A1 in pass A is this implementation's choice and is not counted.
+    # For 64 < n <= 128 pass A is three kernels (two half-row solves and the Gram
+    # pass) and pass B keeps R2^{-1} in LDS.
+    wide = n > 64
     passes = {
-        "passA": dict(kernel="k_passA_mfma", us=pa_us, bytes=8.0 * m * n, flops=m * (2.0 * n * n + n)),
-        "passB": dict(kernel="k_passB", us=pb_us, bytes=16.0 * m * n, flops=1.0 * m * n * n),
+        "passA": dict(kernel="k_passW<0> + k_passW<1> + k_gramW" if wide else "k_passA_mfma", us=pa_us,
+                      bytes=8.0 * m * n, flops=m * (2.0 * n * n + n)),
+        "passB": dict(kernel="k_passB128" if wide else "k_passB", us=pb_us, bytes=16.0 * m * n,
+                      flops=1.0 * m * n * n),
     }
     dom_name = max(passes, key=lambda k: passes[k]["us"])
     dom = passes[dom_name]
