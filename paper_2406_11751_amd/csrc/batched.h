@@ -84,7 +84,10 @@ __global__ __launch_bounds__(kPassThreads, 2) void kb_passW(const PassAArgs* __r
   const BatchItem it = items[blockIdx.x];
   PassAArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
-  passW_body<HALF>(a, it.local, it.count);
+  if constexpr (HALF == 1)
+    passW1_mfma_body(a, it.local, it.count);
+  else
+    passW0_body(a, it.local, it.count);
 }
 
 __global__ __launch_bounds__(kPassThreads) void kb_gramW(const PassAArgs* __restrict__ args,

@@ -5,9 +5,9 @@
 // keeps R2^{-1} in LDS:
 //   k_passW<0>: A1(:, 0:64)   = A(:, 0:64) R11^{-1}              (row solve)
 //   k_passW<1>: A1(:, 64:128) = (A(:, 64:128) - A1(:, 0:64) R12) R22^{-1}
-//             A1(:, 0:64) is re-read one column (512 bytes per wave) at a time,
-//             eight columns ahead; the fma order per element is that of the
-//             128-wide row solve (ascending k), so A1 is the same to the bit.
+//             the rank-64 update on MFMA, the R22 solve per row; the fma
+//             order per element is that of the 128-wide row solve (ascending
+//             k), so A1 is the same to the bit.
 //   k_gramW:  per-workgroup partial Gram matrices of A1 (36 upper 16x16 tiles),
 //             32-row blocks staged in LDS, tiles split over the four waves.
 //   k_passB128: Q = A1 R2^{-1} in place, R2^{-1} (128 x 128) in LDS.
@@ -23,100 +23,6 @@ constexpr int kWH = 64;                      // half width
 constexpr int kWideTri = kWH * (kWH + 1) / 2;  // packed 64-triangle
 constexpr int kWideNB = 8, kWideNT = kWideNB * (kWideNB + 1) / 2, kWideE = kWideNT * 256;
 
-// Rank-64 update of a half row: for k = 0..63, t_j = fma(-x_k, B(k, j), t_j),
-// j = 0..63, with x_k = X[k * ldx + lane] (this lane's row of column k; X is
-// the wave's uniform row base) loaded D columns ahead and B streamed row by row
-// through the scalar path in groups of G (as in trsm_row).
-template <int G, int SYNC, typename P>
-__device__ __forceinline__ void update_row64(double (&t)[kWH], P B, const double* X, int64_t ldx, int lane,
-                                             bool valid) {
-  constexpr int S = kWH * kWH, NG = S / G, D = 8;
-  static_assert(kWH % G == 0, "a group never spans two rows of B");
-  // Column k's address is formed when its load is issued (a uniform base plus
-  // the lane offset), not hoisted into 64 per-lane pointers.
-  auto xload = [&](int k) -> double {
-    int64_t off = (int64_t)k * ldx;
-    asm volatile("" : "+s"(off));
-    return valid ? (X + off)[lane] : 0.0;
-  };
-  double xr[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) xr[d] = xload(d);
-  double cur[G], nxt[G];
-#pragma unroll
-  for (int i = 0; i < G; ++i) cur[i] = B[i];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int p = (g + 1) * G + i;
-      nxt[i] = (p < S) ? B[p] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int p = g * G + i;
-      const int k = p / kWH, j = p % kWH;
-      t[j] = __builtin_fma(-xr[k % D], cur[i], t[j]);
-      if (j == kWH - 1 && k + D < kWH) xr[k % D] = xload(k + D);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    if constexpr (SYNC > 0) {
-      if ((g + 1) % SYNC == 0) __builtin_amdgcn_s_barrier();
-    }
-#pragma unroll
-    for (int i = 0; i < G; ++i) cur[i] = nxt[i];
-  }
-}
-
-// The same update with B (row-major 64 x 64) in LDS: B arrives as wave-uniform
-// 16-byte LDS reads (every lane reads the same address) in groups of eight
-// values, RING groups in flight; LDS reads of a wave return in issue order, so
-// the wait for a group leaves the later groups outstanding.  The fma order per
-// element is that of update_row64.
-template <int RING>
-__device__ __forceinline__ void update_row64_lds(double (&t)[kWH], const double* Bl, const double* X, int64_t ldx,
-                                                 int lane, bool valid) {
-  constexpr int G = 8, NG = kWH * kWH / G, D = 8;
-  static_assert(kWH % G == 0 && NG >= RING, "groups");
-  auto xload = [&](int k) -> double {
-    int64_t off = (int64_t)k * ldx;
-    asm volatile("" : "+s"(off));
-    return valid ? (X + off)[lane] : 0.0;
-  };
-  double xr[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) xr[d] = xload(d);
-  double buf[RING][G];
-#pragma unroll
-  for (int r = 0; r < RING; ++r)
-#pragma unroll
-    for (int i = 0; i < G; ++i) buf[r][i] = Bl[r * G + i];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const int slot = g % RING;
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int p = g * G + i;
-      const int k = p / kWH, j = p % kWH;
-      t[j] = __builtin_fma(-xr[k % D], buf[slot][i], t[j]);
-      if (j == kWH - 1 && k + D < kWH) xr[k % D] = xload(k + D);
-    }
-    // The group's results are pinned here and the memory clobber keeps the LDS
-    // reads of later groups below this point: otherwise the optimizer sinks the
-    // fmas and hoists the reads, and all 4096 values of B are live at once.
-#pragma unroll
-    for (int i = 0; i < G; ++i) asm volatile("" : "+v"(t[(g * G + i) % kWH]));
-    asm volatile("" ::: "memory");
-    if (g + RING < NG) {
-#pragma unroll
-      for (int i = 0; i < G; ++i) buf[slot][i] = Bl[(g + RING) * G + i];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 // Stores columns 0 .. ncols-1 of this lane's half row at W + r0 (ld ldw).
 __device__ __forceinline__ void store_half(double* W, int64_t ldw, const double (&t)[kWH], int64_t r0, int lane,
                                            bool valid, int ncols) {
@@ -129,44 +35,127 @@ __device__ __forceinline__ void store_half(double* W, int64_t ldw, const double 
   }
 }
 
-// HALF 0: first 64 columns; HALF 1: the remaining n - 64 columns.
-template <int HALF>
-__device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk) {
-  __shared__ __attribute__((aligned(16))) double r12s[HALF == 1 ? kWH * kWH : 2];
+// Columns 0..63: A1(:, 0:64) = A(:, 0:64) R11^{-1} (the lane-per-row solve).
+__device__ __forceinline__ void passW0_body(const PassAArgs& a, int bid, int nblk) {
   if (a.info[0] != 0) return;
-  if constexpr (HALF == 1) {
-    for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads) r12s[e] = a.tri_s[2 * kWideTri + e];
-    __syncthreads();
-  }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int64_t panels = (a.m + kWave - 1) / kWave;
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-  const int ncols = HALF == 0 ? kWH : a.n - kWH;
   for (int64_t pg = bid; pg < pgroups; pg += nblk) {
     const int64_t r0 = (pg * kPassWaves + wave) * kWave;
     const bool valid = r0 + lane < a.m;
     double t[kWH];
-    load_row<kWH>(t, a.A + (int64_t)HALF * kWH * a.lda, r0, a.lda, ncols, lane, valid);
+    load_row<kWH>(t, a.A, r0, a.lda, kWH, lane, valid);
     pin_values(t);
-    if constexpr (HALF == 1) {
-      // A per-lane (all equal) base: the LDS reads then take their offsets as
-      // immediates instead of one address register each.
-      int z = 0;
-      asm volatile("" : "+v"(z));
-      update_row64_lds<4>(t, static_cast<const double*>(r12s) + 2 * z, a.W + r0, a.ldw, lane, valid);
-      pin_values(t);
-      trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s + kWideTri)));
-    } else {
-      trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
+    trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
+    pin_values(t);
+    store_half(a.W, a.ldw, t, r0, lane, valid, kWH);
+  }
+}
+
+// Columns 64 .. n-1 with the rank-64 update on MFMA.  For each 16-row block rb
+// and 16-column block cb of the wave's panel, in the transposed form
+//   D'(col, row) = A(row, 64 + col) + sum_k R12(k, col) (-A1(row, k)),
+// the accumulator starts from the A tile and each v_mfma_f64_16x16x4f64 adds
+// four products of ascending k as an fma chain (which is how it rounds), so
+// every entry receives exactly the fmas of the row solve in the same order.
+// Operands: R12 from LDS (row stride 66: the four lane rows hit distinct
+// banks); A1 and A straight from memory in the operand layouts (four 128-byte
+// column segments per load).  Lane l then holds, for block rb, row
+// 16 rb + l % 16 at columns 16 cb + 4 v + l / 16; two rounds of lane swaps
+// (permlane32_swap between register sets s and s + 2, permlane16_swap between
+// s and s + 1) transpose the (lane row, register set) blocks, after which lane
+// l holds row l with column 16 cb + 4 v + s in set s.  The R22 substitution
+// and the store are those of passW_body.
+constexpr int kR12Ld = kWH + 2;
+
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                   false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                   false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+__device__ __forceinline__ void passW1_mfma_body(const PassAArgs& a, int bid, int nblk) {
+  __shared__ double r12s[kWH * kR12Ld];
+  if (a.info[0] != 0) return;
+  for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads)
+    r12s[(e / kWH) * kR12Ld + e % kWH] = a.tri_s[2 * kWideTri + e];
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int64_t panels = (a.m + kWave - 1) / kWave;
+  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+  const int ncols = a.n - kWH;
+  for (int64_t pg = bid; pg < pgroups; pg += nblk) {
+    const int64_t r0 = (pg * kPassWaves + wave) * kWave;
+    double vals[4][16];  // [register set = row block][4 cb + v]
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int64_t row = r0 + 16 * rb + i16;
+      const bool rvalid = row < a.m;
+      int nc = ncols;
+      int64_t lda = a.lda, ldw = a.ldw;
+      asm volatile("" : "+s"(nc), "+s"(lda), "+s"(ldw));
+      d4 acc[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * cb + 4 * v + g;
+          acc[cb][v] = (rvalid && col < nc) ? a.A[row + (int64_t)(kWH + col) * lda] : 0.0;
+        }
+      double bx[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) bx[c] = rvalid ? -a.W[row + (int64_t)(4 * c + g) * ldw] : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(r12s[(4 * c + g) * kR12Ld + 16 * cb + i16], bx[c], acc[cb], 0,
+                                                         0, 0);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vals[rb][4 * cb + v] = acc[cb][v];
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      swap32(vals[0][e], vals[2][e]);
+      swap32(vals[1][e], vals[3][e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      swap16(vals[0][e], vals[1][e]);
+      swap16(vals[2][e], vals[3][e]);
+    }
+    double t[kWH];
+#pragma unroll
+    for (int col = 0; col < kWH; ++col) t[col] = vals[col & 3][4 * (col >> 4) + ((col >> 2) & 3)];
+    const bool valid = r0 + lane < a.m;
     pin_values(t);
-    store_half(a.W + (int64_t)HALF * kWH * a.ldw, a.ldw, t, r0, lane, valid, ncols);
+    trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s + kWideTri)));
+    pin_values(t);
+    store_half(a.W + (int64_t)kWH * a.ldw, a.ldw, t, r0, lane, valid, ncols);
   }
 }
 
 template <int HALF>
 __global__ __launch_bounds__(kPassThreads, 2) void k_passW(PassAArgs a) {
-  passW_body<HALF>(a, blockIdx.x, gridDim.x);
+  if constexpr (HALF == 1)
+    passW1_mfma_body(a, blockIdx.x, gridDim.x);
+  else
+    passW0_body(a, blockIdx.x, gridDim.x);
 }
 
 // Upper 16x16 block tiles of the 128-column Gram, wave w taking tiles w, w+4, ...
