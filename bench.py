@@ -218,7 +218,7 @@ def main():
     # pass) and pass B keeps R2^{-1} in LDS.
     wide = n > 64
     passes = {
-        "passA": dict(kernel="k_passW<0> + k_passW<1> + k_gramW" if wide else "k_passA_mfma", us=pa_us,
+        "passA": dict(kernel="k_passW + k_gramW" if wide else "k_passA_mfma", us=pa_us,
                       bytes=8.0 * m * n, flops=m * (2.0 * n * n + n)),
         "passB": dict(kernel="k_passB128" if wide else "k_passB", us=pb_us, bytes=16.0 * m * n,
                       flops=1.0 * m * n * n),

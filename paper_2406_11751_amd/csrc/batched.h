@@ -78,16 +78,12 @@ __global__ __launch_bounds__(kPassBThreads) void kb_passB(const PassBArgs* __res
   passB_body<NMAX>(a, it.local, it.count);
 }
 
-template <int HALF>
 __global__ __launch_bounds__(kPassThreads, 2) void kb_passW(const PassAArgs* __restrict__ args,
                                                            const BatchItem* __restrict__ items, int32_t* info) {
   const BatchItem it = items[blockIdx.x];
   PassAArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
-  if constexpr (HALF == 1)
-    passW1_mfma_body(a, it.local, it.count);
-  else
-    passW0_body(a, it.local, it.count);
+  passW_body(a, it.local, it.count);
 }
 
 __global__ __launch_bounds__(kPassThreads) void kb_gramW(const PassAArgs* __restrict__ args,

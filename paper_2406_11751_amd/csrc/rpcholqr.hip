@@ -172,11 +172,10 @@ void launch_pass_B(const Plan& p, const PassBArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_passB<NMAX>), dim3(p.PB), dim3(kPassBThreads), 0, st, a);
 }
 
-// Pass A for 64 < n <= 128: both halves of the row solve, then the Gram pass.
+// Pass A for 64 < n <= 128: the two-half row solve, then the Gram pass.
 // Returns the number of Gram partials written.
 int launch_passes_A_wide(const Plan& p, const PassAArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_passW<0>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
-  hipLaunchKernelGGL((k_passW<1>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL(k_passW, dim3(p.PA), dim3(kPassThreads), 0, st, a);
   hipLaunchKernelGGL(k_gramW, dim3(p.PA), dim3(kPassThreads), 0, st, a);
   return p.PA;
 }
@@ -676,8 +675,7 @@ int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, voi
       case 48: hipLaunchKernelGGL((kb_passA<48>), g, blk, 0, st, pa, it, inf); break;
       case 64: hipLaunchKernelGGL((kb_passA<64>), g, blk, 0, st, pa, it, inf); break;
       default:
-        hipLaunchKernelGGL((kb_passW<0>), g, blk, 0, st, pa, it, inf);
-        hipLaunchKernelGGL((kb_passW<1>), g, blk, 0, st, pa, it, inf);
+        hipLaunchKernelGGL(kb_passW, g, blk, 0, st, pa, it, inf);
         hipLaunchKernelGGL(kb_gramW, g, blk, 0, st, pa, it, inf);
         break;
     }

@@ -3,9 +3,9 @@
 // next to the Gram accumulators, so the row solve runs in two halves of 64
 // columns, the Gram matrix is a separate pass over the stored A1, and pass B
 // keeps R2^{-1} in LDS:
-//   k_passW<0>: A1(:, 0:64)   = A(:, 0:64) R11^{-1}              (row solve)
-//   k_passW<1>: A1(:, 64:128) = (A(:, 64:128) - A1(:, 0:64) R12) R22^{-1}
-//             the rank-64 update on MFMA, the R22 solve per row; the fma
+//   k_passW:  A1(:, 0:64)   = A(:, 0:64) R11^{-1}, then
+//             A1(:, 64:128) = (A(:, 64:128) - A1(:, 0:64) R12) R22^{-1}
+//             with the rank-64 update on MFMA (see passW_body); the fma
 //             order per element is that of the 128-wide row solve (ascending
 //             k), so A1 is the same to the bit.
 //   k_gramW:  per-workgroup partial Gram matrices of A1 (36 upper 16x16 tiles),
@@ -35,38 +35,29 @@ __device__ __forceinline__ void store_half(double* W, int64_t ldw, const double 
   }
 }
 
-// Columns 0..63: A1(:, 0:64) = A(:, 0:64) R11^{-1} (the lane-per-row solve).
-__device__ __forceinline__ void passW0_body(const PassAArgs& a, int bid, int nblk) {
-  if (a.info[0] != 0) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-  for (int64_t pg = bid; pg < pgroups; pg += nblk) {
-    const int64_t r0 = (pg * kPassWaves + wave) * kWave;
-    const bool valid = r0 + lane < a.m;
-    double t[kWH];
-    load_row<kWH>(t, a.A, r0, a.lda, kWH, lane, valid);
-    pin_values(t);
-    trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
-    pin_values(t);
-    store_half(a.W, a.ldw, t, r0, lane, valid, kWH);
-  }
-}
-
-// Columns 64 .. n-1 with the rank-64 update on MFMA.  For each 16-row block rb
-// and 16-column block cb of the wave's panel, in the transposed form
+// Row solve of the 128-column class, one 64-row panel per wave:
+//   A1(:, 0:64)   = A(:, 0:64) R11^{-1}                         (lane per row)
+//   A1(:, 64:128) = (A(:, 64:128) - A1(:, 0:64) R12) R22^{-1}
+// The rank-64 update runs on MFMA.  For each 16-row block rb and 16-column
+// block cb, in the transposed form
 //   D'(col, row) = A(row, 64 + col) + sum_k R12(k, col) (-A1(row, k)),
 // the accumulator starts from the A tile and each v_mfma_f64_16x16x4f64 adds
 // four products of ascending k as an fma chain (which is how it rounds), so
-// every entry receives exactly the fmas of the row solve in the same order.
-// Operands: R12 from LDS (row stride 66: the four lane rows hit distinct
-// banks); A1 and A straight from memory in the operand layouts (four 128-byte
-// column segments per load).  Lane l then holds, for block rb, row
-// 16 rb + l % 16 at columns 16 cb + 4 v + l / 16; two rounds of lane swaps
-// (permlane32_swap between register sets s and s + 2, permlane16_swap between
-// s and s + 1) transpose the (lane row, register set) blocks, after which lane
-// l holds row l with column 16 cb + 4 v + s in set s.  The R22 substitution
-// and the store are those of passW_body.
+// every entry receives exactly the fmas of the 128-wide row solve in the same
+// order and A1 is the same to the bit.  R12 comes from LDS (row stride 66: the
+// four lane rows hit distinct banks) and the A tiles straight from memory in
+// the operand layout (four 128-byte column segments per load).
+//
+// Layouts: "row" layout, lane l holds row l of the panel, register set s
+// (s = 0..3) holding columns 16 cb + 4 v + s at index 4 cb + v; "operand"
+// layout, lane l holds in set rb row 16 rb + l % 16 at columns
+// 16 cb + 4 v + l / 16.  The two are block transposes of each other over
+// (lane row l / 16, register set), done by permlane32_swap between sets s and
+// s + 2 and then permlane16_swap between sets s and s + 1, in both directions.
+// So the solved left half goes to the operand layout (where set rb holds the
+// MFMA B operands -A1(row, 4 c + l / 16) of block rb at index c), each block's
+// products replace its operands in the same registers, and the result comes
+// back to the row layout for the R22 solve.
 constexpr int kR12Ld = kWH + 2;
 
 __device__ __forceinline__ void swap32(double& x, double& y) {
@@ -85,8 +76,21 @@ __device__ __forceinline__ void swap16(double& x, double& y) {
   x = __hiloint2double((int)hi[0], (int)lo[0]);
   y = __hiloint2double((int)hi[1], (int)lo[1]);
 }
+// Block transpose between the row and operand layouts (its own inverse).
+__device__ __forceinline__ void transpose_sets(double (&vals)[4][16]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    swap32(vals[0][e], vals[2][e]);
+    swap32(vals[1][e], vals[3][e]);
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    swap16(vals[0][e], vals[1][e]);
+    swap16(vals[2][e], vals[3][e]);
+  }
+}
 
-__device__ __forceinline__ void passW1_mfma_body(const PassAArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk) {
   __shared__ double r12s[kWH * kR12Ld];
   if (a.info[0] != 0) return;
   for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads)
@@ -99,14 +103,30 @@ __device__ __forceinline__ void passW1_mfma_body(const PassAArgs& a, int bid, in
   const int ncols = a.n - kWH;
   for (int64_t pg = bid; pg < pgroups; pg += nblk) {
     const int64_t r0 = (pg * kPassWaves + wave) * kWave;
-    double vals[4][16];  // [register set = row block][4 cb + v]
+    const bool valid = r0 + lane < a.m;
+    double vals[4][16];
+    {
+      double t[kWH];
+      load_row<kWH>(t, a.A, r0, a.lda, kWH, lane, valid);
+      pin_values(t);
+      trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
+      pin_values(t);
+      if (!valid) {
+#pragma unroll
+        for (int j = 0; j < kWH; ++j) t[j] = 0.0;
+      }
+      store_half(a.W, a.ldw, t, r0, lane, valid, kWH);
+#pragma unroll
+      for (int col = 0; col < kWH; ++col) vals[col & 3][4 * (col >> 4) + ((col >> 2) & 3)] = t[col];
+    }
+    transpose_sets(vals);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int64_t row = r0 + 16 * rb + i16;
       const bool rvalid = row < a.m;
       int nc = ncols;
-      int64_t lda = a.lda, ldw = a.ldw;
-      asm volatile("" : "+s"(nc), "+s"(lda), "+s"(ldw));
+      int64_t lda = a.lda;
+      asm volatile("" : "+s"(nc), "+s"(lda));
       d4 acc[4];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
@@ -115,34 +135,21 @@ __device__ __forceinline__ void passW1_mfma_body(const PassAArgs& a, int bid, in
           const int col = 16 * cb + 4 * v + g;
           acc[cb][v] = (rvalid && col < nc) ? a.A[row + (int64_t)(kWH + col) * lda] : 0.0;
         }
-      double bx[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) bx[c] = rvalid ? -a.W[row + (int64_t)(4 * c + g) * ldw] : 0.0;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(r12s[(4 * c + g) * kR12Ld + 16 * cb + i16], bx[c], acc[cb], 0,
-                                                         0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(r12s[(4 * c + g) * kR12Ld + 16 * cb + i16], -vals[rb][c],
+                                                         acc[cb], 0, 0, 0);
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) vals[rb][4 * cb + v] = acc[cb][v];
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      swap32(vals[0][e], vals[2][e]);
-      swap32(vals[1][e], vals[3][e]);
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      swap16(vals[0][e], vals[1][e]);
-      swap16(vals[2][e], vals[3][e]);
-    }
+    transpose_sets(vals);
     double t[kWH];
 #pragma unroll
     for (int col = 0; col < kWH; ++col) t[col] = vals[col & 3][4 * (col >> 4) + ((col >> 2) & 3)];
-    const bool valid = r0 + lane < a.m;
     pin_values(t);
     trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s + kWideTri)));
     pin_values(t);
@@ -150,13 +157,7 @@ __device__ __forceinline__ void passW1_mfma_body(const PassAArgs& a, int bid, in
   }
 }
 
-template <int HALF>
-__global__ __launch_bounds__(kPassThreads, 2) void k_passW(PassAArgs a) {
-  if constexpr (HALF == 1)
-    passW1_mfma_body(a, blockIdx.x, gridDim.x);
-  else
-    passW0_body(a, blockIdx.x, gridDim.x);
-}
+__global__ __launch_bounds__(kPassThreads, 2) void k_passW(PassAArgs a) { passW_body(a, blockIdx.x, gridDim.x); }
 
 // Upper 16x16 block tiles of the 128-column Gram, wave w taking tiles w, w+4, ...
 struct WideTiles {
