@@ -125,6 +125,32 @@ def test_batched_failures_stay_in_their_problem():
     plan.close()
 
 
+def test_batched_failures_in_the_wide_class():
+    # ESKETCH (a zero column beyond 64) and ECHOL (NaN in an unsampled row, column
+    # beyond 64) in 128-column-class problems next to good ones of both classes.
+    m, n, s = 3000, 100, 300
+    good = [gen_usv(m, n, 1e6, 60), gen_usv(4000, 40, 1e4, 61)]
+    bad_sketch = gen_usv(m, n, 1e3, 62)
+    bad_sketch[:, 90] = 0.0
+    bad_chol = gen_usv(m, n, 1e3, 63)
+    missed = sorted(set(range(m)) - set(oracle.sample_indices(m, s, 8).tolist()))[3]
+    bad_chol[missed, 70] = np.nan
+    As_h = [good[0], bad_sketch, good[1], bad_chol]
+    ss = [s, s, 120, s]
+    seeds = [6, 7, 9, 8]
+    announce("failure isolation, 128-column class")
+    plan = rq().BatchedPlan([dev(A) for A in As_h], ss, seeds)
+    info = host(plan.execute(check=False))
+    refs = [oracle.rpcholqr(A, si, sd, nthreads=NTHREADS) for A, si, sd in zip(As_h, ss, seeds)]
+    assert refs[1].status == oracle.ESKETCH and refs[3].status == oracle.ECHOL
+    assert info[1].tolist() == [1, refs[1].index] and info[3].tolist() == [2, refs[3].index]
+    for i in (0, 2):
+        assert info[i].tolist() == [0, -1]
+        assert metrics.rel_fro(host(plan.Qs[i]), refs[i].Q) < TOL
+        assert metrics.rel_fro(host(plan.Rs[i]), refs[i].R) < TOL
+    plan.close()
+
+
 def test_batched_factor_convenience_and_graph_capture():
     probs = MIXED[5:9]
     As_h = [gen_usv(m, n, k, 300 + i) for i, (m, n, s, k) in enumerate(probs)]

@@ -108,6 +108,7 @@ WIDE_CASES = [
     (2000, 128, 1536, 1e6, 25),     # largest s
     (200, 70, 210, 1e3, 26),        # a single row-panel group, m < 4 * 64
     (100003, 112, 336, 1e10, 27),
+    (5000, 80, 160, 1e10, 28),      # s in 129..192: the 12-row register sketch of the wide class
 ]
 
 
