@@ -211,9 +211,7 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int r = l16 + 16 * t;
-        const double v = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
-        vbuf[buf][r] = v;
-        if (WIDE && k < kSketchMaxN && r < s) a.As[r + (int64_t)k * s] = v;
+        vbuf[buf][r] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
       }
     }
     if (lane == 0) {
@@ -255,6 +253,11 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
         // Columns jc <= k are final (reflector k would only add exact zeros to
         // them); waves whose four columns are all final idle until the barrier.
         if (jc > k && jc < n) apply(std::integral_constant<int, KB>{}, k);
+        if constexpr (WIDE && KB0 == 0) {
+          // Keep reflector k (in LDS since the last barrier) in place of sample
+          // column k for phase 2: one value per thread.
+          for (int r = threadIdx.x; r < s; r += kSketchThreads) a.As[r + (int64_t)k * s] = vbuf[k & 1][r];
+        }
         if (k + 1 < n && wave == (((k + 1) & 63) >> 2)) {
           if (kk < 15)
             reflector(std::integral_constant<int, KB>{}, k + 1);
