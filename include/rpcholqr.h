@@ -127,6 +127,29 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
                               rpcholqr_info* info, void* stream, int64_t* idx, double* As, double* Rs,
                               double* A1, double* G1, double* R2);
 
+/* Algorithm "Preconditioned Cholesky-QR" (Section 3.1) with a preconditioner
+ * the caller supplies: A1 = A R_s^{-1}, G1 = A1^T A1 = R2^T R2, Q = A1 R2^{-1},
+ * R = R2 R_s.  rpCholesky-QR is this algorithm with R_s from the sketch; here
+ * R_s is used exactly as given (no sign change, no check of its diagonal: a
+ * singular or badly conditioned R_s shows up as RPCHOLQR_INFO_ECHOL).
+ *   Rs, ldrs    n x n upper triangular, column-major, ldrs >= n (device, read
+ *               only; its strictly lower part is ignored)
+ *   workspace   at least rpcholqr_workspace_bytes(m, n, n, precision) bytes
+ * Other arguments, status returns and info codes as for rpcholqr_factor
+ * (RPCHOLQR_INFO_ESKETCH does not occur). */
+int32_t rpcholqr_precond_factor(int64_t m, int64_t n, const double* A, int64_t lda, const double* Rs,
+                                int64_t ldrs, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
+                                void* workspace, size_t workspace_bytes, rpcholqr_info* info, void* stream);
+
+/* The s sampled row indices of rpcholqr_factor for (m, seed), 0-based, computed
+ * on the host (Algorithm rpCholesky-QR line 2; Section 4: uniform, independent,
+ * with replacement): index r = floor(SplitMix64_r(seed) * m / 2^64), where
+ * SplitMix64_r(seed) = mix64(seed + (r + 1) * 0x9e3779b97f4a7c15).
+ *   idx   host array of s int64 (caller-owned)
+ * Returns RPCHOLQR_EINVAL if m < 1, s < 0 or idx is NULL with s > 0.  Touches no
+ * device. */
+int32_t rpcholqr_sample_indices(int64_t m, int64_t s, uint64_t seed, int64_t* idx);
+
 /* Per-kernel timing with HIP events, for measurement.  While enabled, every
  * factor call records an event on its stream before the first kernel and after
  * each of its NSTAGES kernels (in order: sketch = sample + gather + sketch QR,

@@ -219,12 +219,16 @@ void with_nmax(int nmax, F&& fn) {
   }
 }
 
+// With Rs_in (n x n upper triangular, ld ldrs) the sketch is skipped and R_s is
+// taken as given (Algorithm Preconditioned Cholesky-QR); s is then n.
 int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
                     double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision, void* ws,
                     size_t ws_bytes, rpcholqr_info* info, void* stream, int64_t* idx, double* As,
-                    double* Rs, double* A1, double* G1, double* R2) {
+                    double* Rs, double* A1, double* G1, double* R2, const double* Rs_in = nullptr,
+                    int64_t ldrs = 0) {
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
+  if (Rs_in && ldrs < n) return RPCHOLQR_EINVAL;
   if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
   const bool refine = precision == RPCHOLQR_FP32_REFINE || precision == RPCHOLQR_BF16X2_REFINE;
   if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
@@ -270,10 +274,19 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   sa.idx_out = idx;
   sa.As_out = As;
   sa.Rs_out = Rs;
-  const int64_t gather_blocks = ((int64_t)s * n + kGatherThreads - 1) / kGatherThreads;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
-  if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
-  launch_sketch(p, sa, st);
+  if (Rs_in) {
+    sa.A = Rs_in;
+    sa.lda = ldrs;
+    if (p.nmax == kWideN)
+      hipLaunchKernelGGL((k_precond_setup<kWideN>), dim3(1), dim3(kSketchThreads), 0, st, sa);
+    else
+      hipLaunchKernelGGL((k_precond_setup<kSketchMaxN>), dim3(1), dim3(kSketchThreads), 0, st, sa);
+  } else {
+    const int64_t gather_blocks = ((int64_t)s * n + kGatherThreads - 1) / kGatherThreads;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
+    if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+    launch_sketch(p, sa, st);
+  }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   mark();
 
@@ -734,6 +747,27 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
                               double* A1, double* G1, double* R2) {
   return factor_impl(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, workspace, workspace_bytes, info,
                      stream, idx, As, Rs, A1, G1, R2);
+}
+
+int32_t rpcholqr_precond_factor(int64_t m, int64_t n, const double* A, int64_t lda, const double* Rs,
+                                int64_t ldrs, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
+                                void* workspace, size_t workspace_bytes, rpcholqr_info* info, void* stream) {
+  if (!Rs) return RPCHOLQR_EINVAL;
+  return factor_impl(m, n, n, 0, A, lda, Q, ldq, R, ldr, precision, workspace, workspace_bytes, info, stream,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, Rs, ldrs);
+}
+
+int32_t rpcholqr_sample_indices(int64_t m, int64_t s, uint64_t seed, int64_t* idx) {
+  if (m < 1 || s < 0 || (s > 0 && !idx)) return RPCHOLQR_EINVAL;
+  for (int64_t r = 0; r < s; ++r) {
+    // SplitMix64 output r in counter form, reduced to [0, m) by multiply-high.
+    uint64_t z = seed + ((uint64_t)r + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    idx[r] = (int64_t)(((unsigned __int128)z * (uint64_t)m) >> 64);
+  }
+  return RPCHOLQR_OK;
 }
 
 int32_t rpcholqr_timing_enable(int32_t on) {

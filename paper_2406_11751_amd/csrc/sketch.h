@@ -89,7 +89,9 @@ __device__ __forceinline__ double row16_sum(double p) {
 //   nmax <= 64: one packed triangle (see Tri), nmax rows.
 //   nmax = 128: R11 packed (64 rows), R22 packed (64 rows, from row 64), then
 //               R12 = R(0:64, 64:128) row-major 64 x 64.
-template <int LDR>
+// With NORMALIZE false (a caller-supplied preconditioner, Algorithm
+// Preconditioned Cholesky-QR) R is used as given.
+template <int LDR, bool NORMALIZE = true>
 __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double* Rl) {
   const int n = a.n, nmax = a.nmax;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -97,7 +99,7 @@ __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double*
     double v = 0.0;
     if (i <= j) {
       v = Rl[i * LDR + j];
-      if (Rl[i * LDR + i] < 0.0) v = -v;
+      if (NORMALIZE && Rl[i * LDR + i] < 0.0) v = -v;
     }
     a.Rs[e] = v;
     if (a.Rs_out) a.Rs_out[e] = v;
@@ -107,7 +109,7 @@ __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double*
     if (k >= n || j >= n) return (j == k) ? 1.0 : 0.0;
     const double rkk = Rl[k * LDR + k];
     const double v = Rl[k * LDR + j];
-    return rkk < 0.0 ? -v : v;
+    return (NORMALIZE && rkk < 0.0) ? -v : v;
   };
   auto put_packed = [&](double* dst, int k0, int w) {  // rows k0 .. k0+w-1, columns k0 ..
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
@@ -387,6 +389,24 @@ __device__ __forceinline__ void sketch_qr_generic_body(const SketchArgs& a) {
   sketch_status(a, bad_k);
   if (bad_k >= 0) return;
   sketch_finish<LDR>(a, Rl);
+}
+
+// Algorithm Preconditioned Cholesky-QR with a caller-supplied R_s (n x n
+// upper triangular, column-major, ld a.lda, at a.A): one workgroup writes the
+// numerical status (none yet) and the operands the sketch QR would have
+// written, from R_s as given.
+template <int MAXN>
+__global__ __launch_bounds__(kSketchThreads) void k_precond_setup(SketchArgs a) {
+  constexpr int LDR = MAXN + 1;
+  __shared__ double Rl[MAXN * LDR];
+  const int n = a.n;
+  for (int e = threadIdx.x; e < MAXN * LDR; e += kSketchThreads) {
+    const int i = e / LDR, j = e - i * LDR;
+    Rl[e] = (i < n && j < n && i <= j) ? a.A[i + (int64_t)j * a.lda] : 0.0;
+  }
+  __syncthreads();
+  sketch_status(a, -1);
+  sketch_finish<LDR, false>(a, Rl);
 }
 
 template <int RPT>

@@ -25,6 +25,9 @@ SIGNATURES = {
     "rpcholqr_factor": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz, _vp, _vp]),
     "rpcholqr_factor_debug": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rpcholqr_precond_factor": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz,
+                                       _vp, _vp]),
+    "rpcholqr_sample_indices": (_i32, [_i64, _i64, _u64, ctypes.POINTER(_i64)]),
     "rpcholqr_timing_enable": (_i32, [_i32]),
     "rpcholqr_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), _i32]),
     "rpcholqr_batched_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
@@ -159,6 +162,58 @@ def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, s
             raise RpCholQRError(f"numerical failure {INFO.get(code, code)} at column {index}", code=code,
                                 index=index)
     return (Q, R, info, extra) if debug else (Q, R, info)
+
+
+def precond_factor(A, Rs, *, Q=None, R=None, workspace=None, info=None, stream=None, precision: int = FP64,
+                   check: bool = True):
+    """Algorithm "Preconditioned Cholesky-QR" with the given n x n upper
+    triangular preconditioner Rs (a device float64 tensor, column-major).
+    Returns (Q, R, info) as factor does."""
+    import torch
+
+    lib = load_library()
+    m, n = A.shape
+    if tuple(Rs.shape) != (n, n):
+        raise ValueError(f"Rs must be {n} x {n}")
+    dev = A.device
+    lda, ldrs = _ld(A, m), _ld(Rs, n)
+    if Q is None:
+        Q = colmajor_empty(m, n, dev)
+    if R is None:
+        R = colmajor_empty(n, n, dev)
+    ldq, ldr = _ld(Q, m), _ld(R, n)
+    wsb = workspace_bytes(m, n, n, precision)
+    if wsb == 0:
+        raise RpCholQRError(f"unsupported sizes m={m} n={n} (max n {max_n()})", status=-4)
+    if workspace is None or workspace.numel() * workspace.element_size() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if info is None:
+        info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib.rpcholqr_precond_factor(m, n, _ptr(A), lda, _ptr(Rs), ldrs, _ptr(Q), ldq, _ptr(R), ldr, precision,
+                                     _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(info), st)
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_precond_factor returned {STATUS.get(rc, rc)}", status=rc)
+    if check:
+        torch.cuda.synchronize(dev)
+        code, index = (int(v) for v in info.cpu().tolist())
+        if code != 0:
+            raise RpCholQRError(f"numerical failure {INFO.get(code, code)} at column {index}", code=code,
+                                index=index)
+    return Q, R, info
+
+
+def sample_indices(m: int, s: int, seed: int):
+    """The s sampled row indices of factor() for (m, seed), computed on the host
+    by the library (numpy int64 array)."""
+    import numpy as np
+
+    idx = np.empty(max(s, 0), dtype=np.int64)
+    rc = load_library().rpcholqr_sample_indices(m, s, seed & (2**64 - 1),
+                                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_sample_indices returned {STATUS.get(rc, rc)}", status=rc)
+    return idx
 
 
 class BatchedPlan:

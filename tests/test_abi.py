@@ -68,3 +68,19 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(native, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         native.load_library()
+
+
+def test_host_sample_indices_match_the_oracle():
+    import numpy as np
+
+    import oracle
+    import paper_2406_11751_amd as rq
+
+    for m, s, seed in [(1, 5, 0), (1_000_000, 192, 0), (2**40 + 3, 100, 123456789), (7, 0, 1),
+                       (10**12, 50, 2**64 - 1), (13, 400, 42)]:
+        got = rq.sample_indices(m, s, seed)
+        assert np.array_equal(got, oracle.sample_indices(m, s, seed)), (m, s, seed)
+        assert got.dtype == np.int64 and (s == 0 or (got.min() >= 0 and got.max() < m))
+    with pytest.raises(rq.RpCholQRError):
+        rq.sample_indices(0, 3, 1)
+
