@@ -139,6 +139,43 @@ def test_deterministic_bits():
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
+def test_deterministic_bits_wide():
+    A_h = gen_usv(30000, 112, 1e10, 4)
+    A = dev(A_h)
+    announce("determinism 30000x112")
+    Q1, R1, _ = rq().factor(A, 336, 5)
+    Q2, R2, _ = rq().factor(A, 336, 5)
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+
+
+@pytest.mark.parametrize("m,n,s", [(50000, 64, 192), (20000, 100, 300)])
+def test_single_call_graph_capture(m, n, s):
+    # rpcholqr_factor issues kernels only (no allocation, no memset), so a call
+    # can be captured; every replay must give the eager result.
+    A = dev(gen_usv(m, n, 1e8, 9))
+    announce(f"graph capture {m}x{n}")
+    Q0, R0, _ = rq().factor(A, s, 3)
+    Q = rq().colmajor_empty(m, n, "cuda")
+    R = rq().colmajor_empty(n, n, "cuda")
+    ws = torch.empty(rq().workspace_bytes(m, n, s), dtype=torch.uint8, device="cuda")
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    st = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        rq().factor(A, s, 3, Q=Q, R=R, workspace=ws, info=info, stream=st.cuda_stream, check=False)
+        st.synchronize()
+        with torch.cuda.graph(g, stream=st):
+            rq().factor(A, s, 3, Q=Q, R=R, workspace=ws, info=info, stream=st.cuda_stream, check=False)
+    for rep in range(3):
+        Q.zero_()
+        R.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert info.cpu().tolist() == [0, -1]
+        assert torch.equal(Q, Q0) and torch.equal(R, R0), f"replay {rep}"
+
+
 @pytest.mark.parametrize("pad,off,n", [(13, 0, 24), (14, 0, 24), (14, 1, 24), (13, 0, 100), (14, 1, 100)])
 def test_leading_dimensions(pad, off, n):
     # Odd and even leading dimensions, and an A that starts 8 bytes into its
