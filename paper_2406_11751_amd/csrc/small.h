@@ -199,7 +199,10 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
     }
   }
 
-#pragma unroll
+  // The block loops run as loops (not unrolled): the kernel executes once per
+  // factorization, so its instruction stream is fetched cold and straight-line
+  // code costs more than the loop overhead.
+#pragma unroll 1
   for (int kb = 0; kb < NB; ++kb) {
     const int base = 16 * kb;
     // (a) diagonal block: factor (lanes 0-15) and invert (lanes 16-31).
@@ -259,27 +262,29 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
         store_d(Gs, LD, base, c0, lane, acc);
       }
       __syncthreads();
-      // (c) trailing update of the blocks (bi, bj), kb < bi <= bj.
-      int q = 0;
-#pragma unroll
-      for (int bi = kb + 1; bi < NB; ++bi)
-#pragma unroll
-        for (int bj = bi; bj < NB; ++bj) {
-          if (q % 4 == wave) {
-            d4 acc = load_d(Gs, LD, 16 * bi, 16 * bj, lane);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc = mfma16(-opAT(Gs, LD, base, 16 * bi, c, lane), opB(Gs, LD, base, 16 * bj, c, lane), acc);
-            store_d(Gs, LD, 16 * bi, 16 * bj, lane, acc);
-          }
-          ++q;
+      // (c) trailing update of the blocks (bi, bj), kb < bi <= bj; tile q of
+      // the trailing triangle (row by row) goes to wave q mod 4.
+      const int mt = NB - 1 - kb;
+#pragma unroll 1
+      for (int q = wave; q < mt * (mt + 1) / 2; q += kCholThreads / kWave) {
+        int bi = kb + 1, rem = q;
+        while (rem >= NB - bi) {
+          rem -= NB - bi;
+          ++bi;
         }
+        const int bj = bi + rem;
+        d4 acc = load_d(Gs, LD, 16 * bi, 16 * bj, lane);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc = mfma16(-opAT(Gs, LD, base, 16 * bi, c, lane), opB(Gs, LD, base, 16 * bj, c, lane), acc);
+        store_d(Gs, LD, 16 * bi, 16 * bj, lane, acc);
+      }
       __syncthreads();
     }
   }
 
   // Off-diagonal blocks of T = R2^{-1}, by increasing distance from the diagonal.
-#pragma unroll
+#pragma unroll 1
   for (int dist = 1; dist < NB; ++dist) {
     for (int bi = wave; bi + dist < NB; bi += kCholThreads / kWave) {
       const int bj = bi + dist;
@@ -315,33 +320,33 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   }
   // Line 8: R = R2 R_s, upper block tiles on MFMA; blocks below the diagonal are zero.
   {
-    int q = 0;
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-      for (int bj = bi; bj < NB; ++bj) {
-        if (q % 4 == wave) {
-          d4 acc = {0.0, 0.0, 0.0, 0.0};
-          for (int l = bi; l <= bj; ++l)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              double b;
-              if constexpr (WIDE) {
-                const int r = 16 * l + 4 * c + (lane >> 4), cc = 16 * bj + (lane & 15);
-                b = (r < n && cc < n) ? a.Rs[r + (int64_t)cc * n] : 0.0;
-              } else {
-                b = opB(Rsl, LD, 16 * l, 16 * bj, c, lane);
-              }
-              acc = mfma16(opA(Gs, LD, 16 * bi, 16 * l, c, lane), b, acc);
-            }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * bi + 4 * v + (lane >> 4), j = 16 * bj + (lane & 15);
-            if (i < n && j < n) a.R[i + (int64_t)j * a.ldr] = acc[v];
-          }
-        }
-        ++q;
+#pragma unroll 1
+    for (int q = wave; q < NT; q += kCholThreads / kWave) {
+      int bi = 0, rem = q;
+      while (rem >= NB - bi) {
+        rem -= NB - bi;
+        ++bi;
       }
+      const int bj = bi + rem;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int l = bi; l <= bj; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double b;
+          if constexpr (WIDE) {
+            const int r = 16 * l + 4 * c + (lane >> 4), cc = 16 * bj + (lane & 15);
+            b = (r < n && cc < n) ? a.Rs[r + (int64_t)cc * n] : 0.0;
+          } else {
+            b = opB(Rsl, LD, 16 * l, 16 * bj, c, lane);
+          }
+          acc = mfma16(opA(Gs, LD, 16 * bi, 16 * l, c, lane), b, acc);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * bi + 4 * v + (lane >> 4), j = 16 * bj + (lane & 15);
+        if (i < n && j < n) a.R[i + (int64_t)j * a.ldr] = acc[v];
+      }
+    }
     for (int e = tid; e < n * n; e += kCholThreads) {
       const int i = e % n, j = e / n;
       if (i / 16 > j / 16) a.R[i + (int64_t)j * a.ldr] = 0.0;
