@@ -141,7 +141,7 @@ def main():
         print(f"copied {x.numel() * 8} bytes three times", flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
               "(row sharding over several GPUs is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np

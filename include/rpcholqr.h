@@ -50,7 +50,7 @@ typedef enum {
   RPCHOLQR_EINVAL = -1,      /* n < 1, m < n, s < n, ld* too small, NULL or overlapping buffers */
   RPCHOLQR_EHIP = -2,        /* a HIP runtime call or kernel launch failed */
   RPCHOLQR_EWORKSPACE = -3,  /* workspace NULL or smaller than rpcholqr_workspace_bytes() */
-  RPCHOLQR_EUNSUPPORTED = -4 /* n or s beyond what this build supports (rpcholqr_max_n()) */
+  RPCHOLQR_EUNSUPPORTED = -4 /* n or s beyond what this library supports (rpcholqr_max_n()) */
 } rpcholqr_status;
 
 /* Arithmetic of the passes over A.
@@ -87,7 +87,7 @@ typedef struct {
 /* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
 #define RPCHOLQR_INFO_ECHOL2 3
 
-/* Largest n this build accepts (128).  Sizes this build supports: s <= 1536
+/* Largest n the library accepts (128).  Supported sizes: s <= 1536
  * and n <= 128 for RPCHOLQR_FP64, n <= 64 for the refined precisions; other
  * sizes give RPCHOLQR_EUNSUPPORTED. */
 int32_t rpcholqr_max_n(void);
