@@ -246,193 +246,6 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
   passA_body<NMAX, MODE, GP>(a, blockIdx.x, gridDim.x);
 }
 
-// pass A, LDS-staged ping-pong (NMAX a multiple of 16, <= 64; columns 16-byte
-// aligned: A and lda even).  A workgroup has 8 waves; waves w and w+4 (one SIMD)
-// form a pair that shares one LDS stage holding one panel.  Each wave's panel
-// loop has two halves separated by workgroup barriers: H1 = read its panel from
-// the stage, issue the loads of the partner's next panel into the stage, row
-// solve; H2 = store A1 and contract the Gram tiles.  The partner runs one half
-// behind, so while one wave of a SIMD solves, the other stores and contracts,
-// and every panel's loads are in flight for a whole half.
-//   stage: global_load_lds_dwordx4 moves 16 bytes per lane straight from HBM
-//          into LDS; lanes 0-31 take rows 2i, 2i+1 of column 2c and lanes 32-63
-//          those of column 2c+1, so the stage holds the panel column-major,
-//          element (r, j) at j*64 + r.
-//   Gram:  A1 goes through a quarter-panel buffer per pair (used by one wave of
-//          the pair at a time), element (r, j) at r*NMAX + (j ^ r), which is
-//          conflict-free for the row writes and the MFMA operand reads.
-// Full panels only are staged; the partial last panel is read with plain loads.
-constexpr int kPPThreads = 512;
-constexpr int kPPWaves = kPPThreads / kWave;
-constexpr int kPPPairs = kPPWaves / 2;
-
-template <int NMAX>
-struct PassAPP {
-  static constexpr int STAGE = NMAX * kWave;  // doubles per pair
-  static constexpr int TR = 16 * NMAX;        // doubles per pair
-  static constexpr int LDS_BYTES = kPPPairs * (STAGE + TR) * 8;
-  static constexpr int OCC = NMAX >= 48 ? 1 : 2;  // workgroups per CU
-  static_assert(OCC * LDS_BYTES <= 160 * 1024, "LDS per CU");
-  static_assert(kPPPairs * GramShape<NMAX>::E <= kPPPairs * STAGE, "cross-wave sum reuses the stages");
-};
-
-// Issues the staged loads of the 64-row panel at r0 (columns < n) into stage_w.
-template <int NMAX>
-__device__ __forceinline__ void dma_panel(const double* __restrict__ A, int64_t lda, int n, int64_t r0, int lane,
-                                          double* stage_w) {
-  asm volatile("" : "+s"(n), "+s"(lda));
-  const int half = lane >> 5;
-  const double* base = A + r0 + 2 * (lane & 31) + half * lda;
-#pragma unroll
-  for (int c = 0; c < NMAX / 2; ++c) {
-    if (2 * c < n && 2 * c + half < n)
-      __builtin_amdgcn_global_load_lds((const void*)(base + (int64_t)(2 * c) * lda),
-                                       (__attribute__((address_space(3))) void*)(stage_w + c * 2 * kWave), 16, 0,
-                                       0);
-  }
-}
-
-// Workgroup barrier after this wave's LDS accesses have completed.  No vector
-// memory wait is implied (loads into the stage stay in flight across it).
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-template <int NMAX>
-__global__ __launch_bounds__(kPPThreads, PassAPP<NMAX>::OCC) void k_passA_pp(PassAArgs a) {
-  static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA Gram tiles");
-  constexpr int NB = GramShape<NMAX>::NB, NT = GramShape<NMAX>::NT, E = GramShape<NMAX>::E;
-  constexpr int STAGE = PassAPP<NMAX>::STAGE, TR = PassAPP<NMAX>::TR;
-  __shared__ double stage[kPPPairs * STAGE];
-  __shared__ double trb[kPPPairs * TR];
-  if (a.info[0] != 0) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  const int pair = wave % kPPPairs, role = wave / kPPPairs;  // role 0 runs one half ahead of role 1
-  double* st = stage + pair * STAGE;
-  double* xs = trb + pair * TR;
-  const int64_t panels = (a.m + kWave - 1) / kWave;
-  const int64_t pgroups = (panels + kPPWaves - 1) / kPPWaves;
-  const int64_t iters = (blockIdx.x < pgroups) ? (pgroups - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  auto row0 = [&](int64_t i, int rl) -> int64_t {
-    return (((int64_t)blockIdx.x + i * gridDim.x) * kPPWaves + rl * kPPPairs + pair) * kWave;
-  };
-  d4 acc[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  const int rq = lane >> 4, cq = lane & 15;  // MFMA operand position
-
-  if (role == 0) {
-    if (iters > 0) {
-      const int64_t r0 = row0(0, 0);
-      if (r0 + kWave <= a.m) dma_panel<NMAX>(a.A, a.lda, a.n, r0, lane, st);
-    }
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-  } else {
-    lds_barrier();  // role 1 starts one half later
-  }
-  for (int64_t i = 0; i < iters; ++i) {
-    // H1: take the panel from the stage, refill the stage for the partner, solve.
-    lds_barrier();
-    const int64_t r0 = row0(i, role);
-    const bool full = r0 + kWave <= a.m;
-    const bool valid = r0 + lane < a.m;
-    double t[NMAX];
-    if (full) {
-      int n = a.n;
-      asm volatile("" : "+s"(n));
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j) t[j] = (j < n) ? st[j * kWave + lane] : 0.0;
-    } else {
-      load_row<NMAX>(t, a.A, r0, a.lda, a.n, lane, valid);
-    }
-    pin_values(t);  // the stage has been read: it may be refilled
-    {
-      const int64_t ip = (role == 0) ? i : i + 1;
-      if (ip < iters) {
-        const int64_t r0p = row0(ip, role ^ 1);
-        if (r0p + kWave <= a.m) dma_panel<NMAX>(a.A, a.lda, a.n, r0p, lane, st);
-      }
-    }
-    trsm_row<NMAX, kTriGroup, 0>(t, opaque(as_const(a.tri_s)));
-    pin_values(t);
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);  // the partner's panel has landed in the stage
-    lds_barrier();
-    // H2: store A1 and contract the Gram tiles.
-    if (!valid) {
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
-    }
-    store_a1<NMAX>(a, t, r0, lane, valid);
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      // Lane-dependent LDS offsets are recomputed here rather than hoisted out of
-      // the panel loop, where they would hold registers for the whole kernel.
-      int c = cq;
-      asm volatile("" : "+v"(c));
-      wave_lds_fence();
-      if (rq == h) {
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j) xs[c * NMAX + (j ^ c)] = t[j];
-      }
-      wave_lds_fence();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // 4-row chunks of the quarter panel
-        const int r = 4 * q + rq;
-        double v[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) v[b] = xs[r * NMAX + ((16 * b + c) ^ r)];
-        int tt = 0;
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-          for (int bj = bi; bj < NB; ++bj) {
-            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[tt], 0, 0, 0);
-            ++tt;
-          }
-      }
-    }
-  }
-  if (role == 0) lds_barrier();  // matches role 1's extra barrier
-
-  // Cross-wave sum in fixed order: acc(w) + acc(w + 4) for w < 4, then the four
-  // pair sums in ascending w.  D(i, j) of a tile sits in lane j + 16 (i%4), register i/4.
-  __builtin_amdgcn_s_waitcnt(kWaitVm0);
-  __syncthreads();
-  if (role == 1) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) stage[pair * E + q * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[q][v];
-  }
-  __syncthreads();
-  if (role == 0) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int e = pair * E + q * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15);
-        acc[q][v] = acc[q][v] + stage[e];
-      }
-  }
-  __syncthreads();
-  if (role == 0) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) stage[pair * E + q * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[q][v];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < E; e += kPPThreads) {
-    double v = stage[e];
-#pragma unroll
-    for (int w = 1; w < kPPPairs; ++w) v = v + stage[w * E + e];
-    a.partials[(int64_t)blockIdx.x * E + e] = v;
-  }
-}
-
 struct PassBArgs {
   int64_t m;
   int32_t n;

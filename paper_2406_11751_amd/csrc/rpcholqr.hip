@@ -31,9 +31,6 @@ constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles
 constexpr int kPassAMaxBlocks = 512;
 static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
 constexpr int kPassBMaxBlocks = 2048;
-// The LDS-staged ping-pong pass A (k_passA_pp) is built and tested but not the
-// default: on MI355X it measures slower than the register-load kernel.
-constexpr bool kStagedPassA = false;
 
 struct Plan {
   int nmax = 0, NB = 0, E = 0;
@@ -146,23 +143,10 @@ int device_cus() {
   return cus;
 }
 
-// Pass A launch: the LDS-staged kernel when columns are 16-byte aligned, with
-// one wave of work per SIMD slot the LDS allows; else the register kernel.
-// Returns the number of workgroups launched (= Gram partials written), 0 on error.
+// Pass A launch.  Returns the number of workgroups launched (= Gram partials
+// written).
 template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
 int launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
-  if constexpr (MODE == kSolveGram && GP == kGramF64) {
-    const bool aligned = ((uintptr_t)a.A % 16 == 0) && (a.lda % 2 == 0);
-    const int cus = kStagedPassA ? device_cus() : 0;
-    if (kStagedPassA && aligned && cus > 0) {
-      const int64_t pgroups = (p.panels + kPPWaves - 1) / kPPWaves;
-      const int64_t slots = (int64_t)cus * PassAPP<NMAX>::OCC;
-      int64_t grid = pgroups < slots ? pgroups : slots;
-      if (grid > p.PA) grid = p.PA;
-      hipLaunchKernelGGL((k_passA_pp<NMAX>), dim3((unsigned)grid), dim3(kPPThreads), 0, st, a);
-      return (int)grid;
-    }
-  }
   hipLaunchKernelGGL((k_passA_mfma<NMAX, MODE, GP>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
   return p.PA;
 }
