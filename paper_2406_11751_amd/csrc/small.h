@@ -10,7 +10,7 @@ namespace rpq {
 constexpr int kReduceThreads = 256;
 constexpr int kReduceChunk = 64;  // partials summed per thread in the first level
 constexpr int kMaxPartial2 = 8;   // second-level partials (first-level chunks) at most
-constexpr int kCholThreads = 256;
+constexpr int kCholThreads = 1024;
 constexpr int kCholMaxN = 64;
 
 // First level: partial2[g][e] = sum of partials[p][e] over p in chunk g, in
@@ -50,8 +50,10 @@ struct CholArgs {
 };
 
 // Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
-// four waves, NMAX/16 column blocks of 16.  The matrices are row-major with a
-// padded row stride (placement below).  Per block kb:
+// sixteen waves (the block products of a step are spread over all of them, and
+// each thread has few Gram partial loads), NMAX/16 column blocks of 16.  The
+// matrices are row-major with a padded row stride (placement below).  Per
+// block kb:
 //   (a) wave 0 factors the 16x16 diagonal block and inverts it in the same
 //       sweep: lanes 0-15 hold the columns of the block, lanes 16-31 the rows of
 //       the identity; step k scales register k by 1/R(k,k) (lane k gets R(k,k))
@@ -108,7 +110,8 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   constexpr int LD = NMAX + 1;               // LDS row stride
   constexpr int TLD = WIDE ? NMAX : LD;      // row stride of R2^{-1}
   constexpr int PER = (E + kCholThreads - 1) / kCholThreads;  // Gram entries per thread
-  constexpr int PCH = PER < 10 ? PER : 10;                    // entries per assembly round
+  constexpr int PCH_MAX = WIDE ? 5 : 10;                      // registers: PCH x kMaxPartial2 loads
+  constexpr int PCH = PER < PCH_MAX ? PER : PCH_MAX;          // entries per assembly round
   static_assert(NMAX % 16 == 0 && (NMAX <= kCholMaxN || NMAX == 2 * kCholMaxN), "block size");
   __shared__ double Gs[NMAX * LD];                // G1, then R2 (upper)
   __shared__ double Tsl[WIDE ? 1 : NMAX * LD];    // R2^{-1} (upper), NMAX <= 64
@@ -132,7 +135,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   // column.  The loads are unconditional (clamped in bounds) and are issued
   // before the partial Gram loads below, so that both sets are in flight
   // together; they are placed in LDS after the assembly.
-  constexpr int U = WIDE ? 1 : NMAX * NMAX / kCholThreads;
+  constexpr int U = WIDE ? 1 : (NMAX * NMAX + kCholThreads - 1) / kCholThreads;
   double rv[U];
   if constexpr (!WIDE) {
 #pragma unroll
@@ -186,6 +189,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = tid + u * kCholThreads;
+      if (e >= NMAX * NMAX) break;
       const int i = e % NMAX, j = e / NMAX;
       Rsl[i * LD + j] = (i <= j && j < n) ? rv[u] : 0.0;
       Tsl[i * LD + j] = 0.0;
