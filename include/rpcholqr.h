@@ -107,7 +107,9 @@ size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precisi
  *               256-byte aligned; contents on entry are ignored
  *   info        device rpcholqr_info receiving the numerical outcome
  *   stream      hipStream_t as void*
- * The result is deterministic: the same inputs give the same bits. */
+ * The result is deterministic: the same inputs give the same bits.  The call
+ * allocates nothing and issues only kernel launches on `stream`, so a stream
+ * capture records it into a HIP graph whose replays give the same bits. */
 int32_t rpcholqr_factor(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
                         double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
                         void* workspace, size_t workspace_bytes, rpcholqr_info* info, void* stream);
