@@ -285,7 +285,10 @@ __device__ __forceinline__ void passB_body(const PassBArgs& a, int bid, int nblk
   }
   const int64_t blocks = (a.m + 15) / 16;
   const int64_t nw = (int64_t)nblk * (kPassBThreads / kWave);
-  for (int64_t blk = (int64_t)bid * (kPassBThreads / kWave) + wave; blk < blocks; blk += nw) {
+  for (int64_t it = (int64_t)bid * (kPassBThreads / kWave) + wave; it < blocks; it += nw) {
+    // Last row blocks first: pass A wrote A1 in ascending row order, so its
+    // last rows are the ones still in the memory-side cache.
+    const int64_t blk = blocks - 1 - it;
     const int64_t row = blk * 16 + i16;
     const bool rvalid = row < a.m;
     double x[NKC];

@@ -210,8 +210,11 @@ __device__ __forceinline__ void gram_loop(const PassAArgs& a, int bid, int nblk,
   constexpr int U = kGramRows * 2 * kWH / kPassThreads;
   const int64_t blocks = (a.m + kGramRows - 1) / kGramRows;
   double nx[U];
+  // Row blocks are taken last first: k_passW wrote A1 in ascending row order,
+  // so its last rows are still in the memory-side cache, and the first rows,
+  // read last here, are then in the cache for k_passB128, which reads forward.
   auto fetch = [&](int64_t blk) __attribute__((always_inline)) {
-    const int64_t r0 = blk * kGramRows;
+    const int64_t r0 = (blk < blocks ? blocks - 1 - blk : 0) * kGramRows;
     int n = a.n;
     asm volatile("" : "+s"(n));
 #pragma unroll
