@@ -209,11 +209,24 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     const double tau = (beta - alpha) / beta;
     if (q == (k & 3)) {
       // Every slot is written (zero outside rows k .. s-1), so that the
-      // reflector's readers need no row mask.
+      // reflector's readers need no row mask.  In the 128-column kernel the
+      // lane's base address is made opaque so that slot t is an immediate
+      // offset from it: per-slot addresses hoisted out of the step loop spill
+      // there, and their reloads would sit on the step's critical path.
+      if constexpr (WIDE) {
+        double* vb = &vbuf[buf][l16];
+        asm volatile("" : "+v"(vb));
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int r = l16 + 16 * t;
-        vbuf[buf][r] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+        for (int t = 0; t < RPT; ++t) {
+          const int r = l16 + 16 * t;
+          vb[16 * t] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int r = l16 + 16 * t;
+          vbuf[buf][r] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+        }
       }
     }
     if (lane == 0) {
