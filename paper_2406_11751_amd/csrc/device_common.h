@@ -13,7 +13,6 @@ constexpr int kWave = 64;
 // s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
 // lgkmcnt 11:8; a field at its maximum does not wait).
 constexpr int kWaitLgkm0 = 0xC07F;  // lgkmcnt(0) only
-constexpr int kWaitVm0 = 0x0F70;    // vmcnt(0) only
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));

@@ -38,7 +38,6 @@ __device__ __forceinline__ void static_for(F&& f) {
 constexpr int kSketchWaves = 16;
 constexpr int kSketchThreads = kSketchWaves * kWave;
 constexpr int kSketchMaxN = 64;  // 16 waves x 4 rows of 16 lanes; R_s staged in LDS as 64 x 65
-constexpr int kSketchLdr = kSketchMaxN + 1;
 constexpr int kGatherThreads = 256;
 
 struct SketchArgs {
