@@ -84,3 +84,15 @@ def test_host_sample_indices_match_the_oracle():
     with pytest.raises(rq.RpCholQRError):
         rq.sample_indices(0, 3, 1)
 
+
+
+def test_bench_rejects_several_gpus():
+    # The benchmark measures one GPU; asking for more exits with a message
+    # (before touching any device).
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
