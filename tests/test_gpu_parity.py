@@ -139,6 +139,19 @@ def test_deterministic_bits():
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
+# One case per register-sketch class (4, 8, 12, 16 and 24 sample rows per lane)
+# and a ragged s: the debug entry point (which also copies out the
+# intermediates) must give the same Q and R bits as the plain one.
+@pytest.mark.parametrize("m,n,s", [(5000, 20, 60), (7001, 40, 120), (100000, 64, 192), (9000, 48, 250),
+                                   (20000, 64, 384), (3000, 7, 21)])
+def test_debug_entry_matches_plain_entry(m, n, s):
+    A = dev(gen_usv(m, n, 1e9, 17))
+    announce(f"debug vs plain {m}x{n} s={s}")
+    Q1, R1, _ = rq().factor(A, s, 4)
+    Q2, R2, _, _ = rq().factor(A, s, 4, debug=True)
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+
+
 def test_deterministic_bits_wide():
     A_h = gen_usv(30000, 112, 1e10, 4)
     A = dev(A_h)
