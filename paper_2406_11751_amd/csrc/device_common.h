@@ -59,6 +59,35 @@ __device__ __forceinline__ void wave_lds_fence() {
 // to back (NMAX(NMAX+1)/2 doubles).  Beyond n the triangle is the identity.
 __host__ __device__ constexpr int tri_row_start(int k, int nmax) { return k * nmax - k * (k - 1) / 2; }
 
+// Writes the operands of the row-wise solves with an upper triangular U of
+// order n (element (k, j) given by u(k, j), identity beyond n), padded to nmax:
+//   nmax <= 64: one packed triangle (below), nmax rows;
+//   nmax = 128: the packed triangles of U11 = U(0:64, 0:64) and U22 =
+//               U(64:128, 64:128), then U12 = U(0:64, 64:128) row-major 64 x 64
+//               (nmax (nmax + 1) / 2 doubles in both cases).
+// Every thread of the block takes part.
+template <typename F>
+__device__ __forceinline__ void write_solve_operands(double* dst, int n, int nmax, F&& u) {
+  auto un = [&](int k, int j) -> double { return (k >= n || j >= n) ? ((j == k) ? 1.0 : 0.0) : u(k, j); };
+  auto put_packed = [&](double* out, int k0, int w) {  // rows k0 .. k0+w-1, columns k0 ..
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+      const int k = e / w, j = e - k * w;
+      if (j < k) continue;
+      const double v = (j == k) ? 1.0 / un(k0 + k, k0 + k) : un(k0 + k, k0 + j);
+      out[tri_row_start(k, w) + (j - k)] = v;
+    }
+  };
+  if (nmax <= 64) {
+    put_packed(dst, 0, nmax);
+  } else {
+    constexpr int H = 64;
+    put_packed(dst, 0, H);
+    put_packed(dst + H * (H + 1) / 2, H, H);
+    double* u12 = dst + H * (H + 1);
+    for (int e = threadIdx.x; e < H * H; e += blockDim.x) u12[e] = un(e / H, H + e % H);
+  }
+}
+
 template <int NMAX>
 struct Tri {
   static constexpr int size = NMAX * (NMAX + 1) / 2;

@@ -96,7 +96,9 @@ __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[N
 //     (A1 rounded to float and split into bfloat16 hi + lo, G ~ hi^T hi +
 //     hi^T lo + lo^T hi on v_mfma_f32_16x16x16bf16_1k, FP32 accumulation).
 // LDS per wave: a half panel (32 rows) of A1, row stride NMAX+1 elements.
-constexpr int kSolveGram = 0, kGramOnly = 1;
+// MODE kSolveOnly: A1 = A U^{-1} stored in W, no Gram (the substitution form of
+//                  line 6, Q = A1 R2^{-1}, run in place with A = W).
+constexpr int kSolveGram = 0, kGramOnly = 1, kSolveOnly = 2;
 constexpr int kBfLdr = 36;  // bf16 elements per column in the BF16x2 staging (32 rows + pad)
 
 // bfloat16 of a float, round to nearest even (finite inputs).
@@ -133,7 +135,7 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
     double t[NMAX];
     load_row<NMAX>(t, a.A, r0, a.lda, a.n, lane, valid);
     pin_values(t);
-    if constexpr (MODE == kSolveGram) {
+    if constexpr (MODE == kSolveGram || MODE == kSolveOnly) {
       trsm_row<NMAX, kTriGroup, kTriSync>(t, opaque(as_const(a.tri_s)));
       pin_values(t);
       if (!valid) {
@@ -142,6 +144,7 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
       }
       store_a1<NMAX>(a, t, r0, lane, valid);
     }
+    if constexpr (MODE == kSolveOnly) continue;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if constexpr (GP == kGramF64) {
@@ -227,6 +230,7 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
       }
     }
   }
+  if constexpr (MODE == kSolveOnly) return;
   __syncthreads();
   // Result element (i, j) of a 16x16 tile sits in lane j + 16 (i mod 4), register
   // i / 4 for the FP64 MFMA, and in lane j + 16 (i / 4), register i mod 4 for FP32.

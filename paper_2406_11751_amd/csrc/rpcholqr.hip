@@ -37,7 +37,7 @@ struct Plan {
   int64_t panels = 0;
   int PA = 0, PB = 0, G2 = 0;
   int rpt = 0;  // sample rows per lane in the register sketch QR; 0 = generic kernel
-  size_t off_tri = 0, off_tri2 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0, off_R1 = 0;
+  size_t off_tri = 0, off_tri2 = 0, off_tri3 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0, off_R1 = 0;
   size_t total = 0;
 };
 
@@ -79,6 +79,8 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
   off = align256(off + tri);
   p->off_tri2 = off;
   off = align256(off + (size_t)p->nmax * p->nmax * sizeof(double));
+  p->off_tri3 = off;  // R2 as row-solve operands (substitution form of line 6)
+  off = align256(off + tri);
   p->off_Rs = off;
   off = align256(off + (size_t)n * n * sizeof(double));
   p->off_part = off;
@@ -229,6 +231,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   char* base = (char*)ws;
   double* tri = (double*)(base + p.off_tri);
   double* tri2 = (double*)(base + p.off_tri2);
+  double* tri3 = (double*)(base + p.off_tri3);
   double* Rs_ws = (double*)(base + p.off_Rs);
   double* part = (double*)(base + p.off_part);
   double* part2 = (double*)(base + p.off_part2);
@@ -325,6 +328,12 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   ca.G1_out = G1;
   ca.R2_out = R2;
   ca.fail_code = RPCHOLQR_INFO_ECHOL;
+  // With a caller's preconditioner kappa(A1) has no bound, so line 6 is solved
+  // by row-wise substitution with R2, whose residual does not grow with
+  // kappa(R2) (Theorem t_perturb1); with the sketch's R_s, kappa(A1) is small
+  // (Lemma l_31) and the product with the explicit R2^{-1} is used.
+  const bool substitute = Rs_in != nullptr;
+  ca.tri_out = substitute ? tri3 : nullptr;
   auto cholesky = [&](const CholArgs& c) {
     if (p.nmax == kWideN) {
       hipLaunchKernelGGL((k_cholesky<kWideN>), dim3(1), dim3(kCholThreads), 0, st, c);
@@ -353,7 +362,18 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
     else
       with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
   };
-  pass_b();
+  if (substitute) {
+    PassAArgs ps = pa;
+    ps.A = Q;
+    ps.lda = ldq;
+    ps.tri_s = tri3;
+    if (p.nmax == kWideN)
+      hipLaunchKernelGGL(k_passW, dim3(p.PA), dim3(kPassThreads), 0, st, ps);
+    else
+      with_nmax(p.nmax, [&](auto nm) { launch_passes_A<decltype(nm)::value, kSolveOnly>(p, ps, st); });
+  } else {
+    pass_b();
+  }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
 
   if (refine) {

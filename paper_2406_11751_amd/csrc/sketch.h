@@ -83,11 +83,9 @@ __device__ __forceinline__ double row16_sum(double p) {
 }
 
 // Sign-normalize R_s (negate rows with a negative diagonal; exact) and write
-// the triangle operands of the row solves, the column-major copy and the
-// optional output.  Rl holds R row-major with row stride LDR.
-//   nmax <= 64: one packed triangle (see Tri), nmax rows.
-//   nmax = 128: R11 packed (64 rows), R22 packed (64 rows, from row 64), then
-//               R12 = R(0:64, 64:128) row-major 64 x 64.
+// the triangle operands of the row solves (write_solve_operands), the
+// column-major copy and the optional output.  Rl holds R row-major with row
+// stride LDR.
 // With NORMALIZE false (a caller-supplied preconditioner, Algorithm
 // Preconditioned Cholesky-QR) R is used as given.
 template <int LDR, bool NORMALIZE = true>
@@ -103,30 +101,12 @@ __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double*
     a.Rs[e] = v;
     if (a.Rs_out) a.Rs_out[e] = v;
   }
-  // element (k, j) of the sign-normalized R, identity beyond n
-  auto rn = [&](int k, int j) -> double {
-    if (k >= n || j >= n) return (j == k) ? 1.0 : 0.0;
+  // element (k, j) of the sign-normalized R
+  write_solve_operands(a.tri, n, nmax, [&](int k, int j) -> double {
     const double rkk = Rl[k * LDR + k];
     const double v = Rl[k * LDR + j];
     return (NORMALIZE && rkk < 0.0) ? -v : v;
-  };
-  auto put_packed = [&](double* dst, int k0, int w) {  // rows k0 .. k0+w-1, columns k0 ..
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-      const int k = e / w, j = e - k * w;
-      if (j < k) continue;
-      const double v = (j == k) ? 1.0 / rn(k0 + k, k0 + k) : rn(k0 + k, k0 + j);
-      dst[tri_row_start(k, w) + (j - k)] = v;
-    }
-  };
-  if (nmax <= 64) {
-    put_packed(a.tri, 0, nmax);
-  } else {
-    constexpr int H = 64;
-    put_packed(a.tri, 0, H);
-    put_packed(a.tri + H * (H + 1) / 2, H, H);
-    double* r12 = a.tri + H * (H + 1);
-    for (int e = threadIdx.x; e < H * H; e += blockDim.x) r12[e] = rn(e / H, H + e % H);
-  }
+  });
 }
 
 __device__ __forceinline__ void sketch_status(const SketchArgs& a, int bad_k) {
@@ -254,6 +234,11 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     if (l16 == (k & 15) && jc > k && jc < n) Rl[k * LDR + jc] = W[KB];
   };
 
+  // The first failed reflector ends the sweep: every wave reads bad[k & 1] at
+  // the top of step k (stable there, see bad) and so stops at the same step;
+  // `stopped` then skips the remaining 16-step blocks, whose first step would
+  // otherwise look at the other bad slot and go on with a stale reflector.
+  bool stopped = false;
   // Steps 16 KB0 .. 16 KB0 + 63 of the sweep (the columns of W are jc).
   auto sweep = [&](auto kb0) __attribute__((always_inline)) {
     constexpr int KB0 = decltype(kb0)::value;
@@ -261,9 +246,14 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     __syncthreads();
     static_for<4>([&](auto kbI) __attribute__((always_inline)) {
       constexpr int KB = KB0 + decltype(kbI)::value;
+      if (stopped) return;
       for (int kk = 0; kk < 16; ++kk) {
         const int k = 16 * KB + kk;
-        if (k >= n || bad[k & 1] >= 0) break;
+        if (k >= n) break;
+        if (bad[k & 1] >= 0) {
+          stopped = true;
+          break;
+        }
         // Columns jc <= k are final (reflector k would only add exact zeros to
         // them); waves whose four columns are all final idle until the barrier.
         if (jc > k && jc < n) apply(std::integral_constant<int, KB>{}, k);

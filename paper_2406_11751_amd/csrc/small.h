@@ -47,6 +47,8 @@ struct CholArgs {
   double* G1_out;       // optional n x n, ld n (upper triangle)
   double* R2_out;       // optional n x n, ld n
   int32_t fail_code;    // info code for a failed pivot (ECHOL, or ECHOL2 in a second pass)
+  double* tri_out;      // optional: R2 as row-solve operands (write_solve_operands), for a
+                        // substitution Q = A1 R2^{-1}
 };
 
 // Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
@@ -311,6 +313,7 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
       a.R2_out[e] = (i <= j) ? Gs[i * LD + j] : 0.0;
     }
   }
+  if (a.tri_out) write_solve_operands(a.tri_out, n, NMAX, [&](int k, int j) -> double { return Gs[k * LD + j]; });
   // T2 for pass B: NMAX x NMAX row-major, zero outside the n x n upper triangle.
   if constexpr (!WIDE) {
     for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {

@@ -115,6 +115,21 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _workspace(nbytes, workspace, dev, stream):
+    """The caller's workspace if it is large enough, else a new one.  A new one
+    used on a caller's stream is marked as in use on that stream, so that the
+    caching allocator does not hand its memory to other work before the
+    kernels launched there have finished with it."""
+    import torch
+
+    if workspace is not None and workspace.numel() * workspace.element_size() >= nbytes:
+        return workspace
+    workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if stream is not None:
+        workspace.record_stream(torch.cuda.ExternalStream(stream, device=dev))
+    return workspace
+
+
 def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, stream=None,
            precision: int = FP64, check: bool = True, debug: bool = False):
     """Thin QR A = Q R by rpCholesky-QR on the GPU.
@@ -138,8 +153,7 @@ def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, s
     wsb = workspace_bytes(m, n, s, precision)
     if wsb == 0:
         raise RpCholQRError(f"unsupported sizes m={m} n={n} s={s} (max n {max_n()})", status=-4)
-    if workspace is None or workspace.numel() * workspace.element_size() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    workspace = _workspace(wsb, workspace, dev, stream)
     if info is None:
         info = torch.empty(2, dtype=torch.int32, device=dev)
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)
@@ -185,8 +199,7 @@ def precond_factor(A, Rs, *, Q=None, R=None, workspace=None, info=None, stream=N
     wsb = workspace_bytes(m, n, n, precision)
     if wsb == 0:
         raise RpCholQRError(f"unsupported sizes m={m} n={n} (max n {max_n()})", status=-4)
-    if workspace is None or workspace.numel() * workspace.element_size() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    workspace = _workspace(wsb, workspace, dev, stream)
     if info is None:
         info = torch.empty(2, dtype=torch.int32, device=dev)
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)

@@ -218,6 +218,24 @@ def test_esketch_zero_column(n, col):
     assert oracle.rpcholqr(A_h, 3 * n, 0).index == col
 
 
+# Two zero columns: the first failure must end the sweep.  The second column lies
+# in a later 16-step block (and, for n = 100, in phase 3 of the 128-column
+# sketch), where a sweep that went on would report it instead.  s = 400 takes
+# the generic sketch kernel.
+@pytest.mark.parametrize("n,s,cols", [(24, 72, (3, 17)), (40, 120, (17, 33)), (24, 400, (3, 17)),
+                                      (100, 300, (3, 17)), (100, 300, (65, 81)), (100, 300, (33, 99))])
+def test_esketch_first_of_two_zero_columns(n, s, cols):
+    A_h = gen_usv(3000, n, 1e3, 5)
+    for c in cols:
+        A_h[:, c] = 0.0
+    announce(f"ESKETCH zero columns {cols} of {n}, s={s}")
+    ref = oracle.rpcholqr(A_h, s, 0)
+    assert ref.status == oracle.ESKETCH and ref.index == cols[0]
+    with pytest.raises(rq().RpCholQRError) as e:
+        rq().factor(dev(A_h), s, 0)
+    assert e.value.code == 1 and e.value.index == cols[0]
+
+
 @pytest.mark.parametrize("n,col", [(12, 3), (80, 70)])
 def test_echol_nonfinite_unsampled_row(n, col):
     m, s = 2000, 3 * n
@@ -276,6 +294,26 @@ def test_argument_errors():
     assert call() == 0
     torch.cuda.synchronize()
     assert info.cpu().tolist() == [0, -1]
+
+
+def test_factor_on_a_caller_stream():
+    # The workspace allocated inside factor() is used on the caller's stream and
+    # freed on return (check=False); the result must still be the plain call's.
+    m, n, s = 200000, 48, 144
+    A_h = gen_usv(m, n, 1e6, 13)
+    A = dev(A_h)
+    announce("caller stream")
+    Q0, R0, _ = rq().factor(A, s, 3)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(3):
+        outs.append(rq().factor(A, s, 3, stream=side.cuda_stream, check=False))
+        torch.empty(1 << 22, dtype=torch.uint8, device="cuda").fill_(255)  # reuse freed memory on the default stream
+    side.synchronize()
+    for Q, R, info in outs:
+        assert info.cpu().tolist() == [0, -1]
+        assert torch.equal(Q, Q0) and torch.equal(R, R0)
 
 
 def test_timing_api_counts_calls():
