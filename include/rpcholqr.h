@@ -143,6 +143,28 @@ int32_t rpcholqr_precond_factor(int64_t m, int64_t n, const double* A, int64_t l
                                 int64_t ldrs, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
                                 void* workspace, size_t workspace_bytes, rpcholqr_info* info, void* stream);
 
+/* rpcholqr_factor without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The call allocates nothing: its workspace
+ * is a static device array of RPCHOLQR_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on every GPU it runs this call on, until the process ends
+ * (its address is looked up on the first call on each device).
+ *   Arguments, status returns, info codes and asynchrony as for
+ *   rpcholqr_factor, on the current device.
+ *   Sizes: as for rpcholqr_factor.  If the sizes need more workspace than the
+ *   array holds with the usual number of Gram partials, fewer (larger) partials
+ *   are used, so Q and R then agree with rpcholqr_factor to rounding (about
+ *   1e-15) rather than to the bit; sizes whose workspace does not fit even with
+ *   one partial return RPCHOLQR_EWORKSPACE.
+ *   Every call on a GPU uses that GPU's one array and leaves its contents
+ *   behind (nothing in it needs to start at zero): calls that overlap in time on
+ *   one GPU (different streams, host threads or processes sharing the library
+ *   instance) race and give undefined results; serialize them. */
+#define RPCHOLQR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t rpcholqr_factor_noalloc(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
+                                double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
+                                rpcholqr_info* info, void* stream);
+
 /* The s sampled row indices of rpcholqr_factor for (m, seed), 0-based, computed
  * on the host (Algorithm rpCholesky-QR line 2; Section 4: uniform, independent,
  * with replacement): index r = floor(SplitMix64_r(seed) * m / 2^64), where

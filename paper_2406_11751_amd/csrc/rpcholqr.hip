@@ -8,6 +8,7 @@
 #include <array>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 #include <cstdint>
@@ -211,7 +212,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
                     double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision, void* ws,
                     size_t ws_bytes, rpcholqr_info* info, void* stream, int64_t* idx, double* As,
                     double* Rs, double* A1, double* G1, double* R2, const double* Rs_in = nullptr,
-                    int64_t ldrs = 0) {
+                    int64_t ldrs = 0, int64_t pa_cap = kPassAMaxBlocks, bool timed = true) {
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
   if (Rs_in && ldrs < n) return RPCHOLQR_EINVAL;
@@ -219,7 +220,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   const bool refine = precision == RPCHOLQR_FP32_REFINE || precision == RPCHOLQR_BF16X2_REFINE;
   if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
   Plan p;
-  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, refine)) return RPCHOLQR_EUNSUPPORTED;
+  if (!make_plan(m, n, s, &p, pa_cap, false, refine)) return RPCHOLQR_EUNSUPPORTED;
   const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
   if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
     return RPCHOLQR_EINVAL;
@@ -237,7 +238,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   double* part2 = (double*)(base + p.off_part2);
   double* R1 = (double*)(base + p.off_R1);
   int32_t* inf = (int32_t*)info;
-  hipEvent_t* ev = timing_slot();
+  hipEvent_t* ev = timed ? timing_slot() : nullptr;
   int stage = 0;
   auto mark = [&]() {
     if (ev) (void)hipEventRecord(ev[stage++], st);
@@ -405,6 +406,42 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   }
   mark();
   return RPCHOLQR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace for callers that cannot allocate (rpcholqr_factor_noalloc): one
+// static device array per GPU.  In host code `scratch` only names the symbol;
+// its device address on the current device comes from hipGetSymbolAddress,
+// taken once per device on the first call there and kept in g_scratch.
+constexpr size_t kScratchBytes = RPCHOLQR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, or nullptr.
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+
+// The largest pass-A partial count (a power of two, at most kPassAMaxBlocks)
+// whose workspace fits the scratch array, or 0 if none does.
+int64_t noalloc_pa_cap(int64_t m, int64_t n, int64_t s, bool refine) {
+  for (int64_t cap = kPassAMaxBlocks; cap >= 1; cap /= 2) {
+    Plan p;
+    if (!make_plan(m, n, s, &p, cap, false, refine)) return -1;
+    if (p.total <= kScratchBytes) return cap;
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +788,21 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
                               double* A1, double* G1, double* R2) {
   return factor_impl(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, workspace, workspace_bytes, info,
                      stream, idx, As, Rs, A1, G1, R2);
+}
+
+int32_t rpcholqr_factor_noalloc(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
+                                double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
+                                rpcholqr_info* info, void* stream) {
+  if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n || !A || !Q || !R || !info) return RPCHOLQR_EINVAL;
+  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
+    return RPCHOLQR_EUNSUPPORTED;
+  const int64_t cap = noalloc_pa_cap(m, n, s, precision != RPCHOLQR_FP64);
+  if (cap < 0) return RPCHOLQR_EUNSUPPORTED;
+  if (cap == 0) return RPCHOLQR_EWORKSPACE;
+  void* ws = scratch_address();
+  if (!ws) return RPCHOLQR_EHIP;
+  return factor_impl(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, ws, kScratchBytes, info, stream, nullptr,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, cap, false);
 }
 
 int32_t rpcholqr_precond_factor(int64_t m, int64_t n, const double* A, int64_t lda, const double* Rs,

@@ -25,6 +25,7 @@ SIGNATURES = {
     "rpcholqr_factor": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz, _vp, _vp]),
     "rpcholqr_factor_debug": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rpcholqr_factor_noalloc": (_i32, [_i64, _i64, _i64, _u64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _vp]),
     "rpcholqr_precond_factor": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _sz,
                                        _vp, _vp]),
     "rpcholqr_sample_indices": (_i32, [_i64, _i64, _u64, ctypes.POINTER(_i64)]),
