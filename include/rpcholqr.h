@@ -87,9 +87,9 @@ typedef struct {
 /* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
 #define RPCHOLQR_INFO_ECHOL2 3
 
-/* Largest n the library accepts (128).  Supported sizes: s <= 1536
- * and n <= 128 for RPCHOLQR_FP64, n <= 64 for the refined precisions; other
- * sizes give RPCHOLQR_EUNSUPPORTED. */
+/* Largest n the library accepts (512).  Supported sizes: s <= 1536 and
+ * n <= 512 for RPCHOLQR_FP64, n <= 64 for the refined precisions, n <= 128 in
+ * the batched entry points; other sizes give RPCHOLQR_EUNSUPPORTED. */
 int32_t rpcholqr_max_n(void);
 
 /* Device workspace in bytes needed by rpcholqr_factor / rpcholqr_factor_debug
@@ -130,8 +130,10 @@ int32_t rpcholqr_factor_debug(int64_t m, int64_t n, int64_t s, uint64_t seed, co
                               double* A1, double* G1, double* R2);
 
 /* Algorithm "Preconditioned Cholesky-QR" (Section 3.1) with a preconditioner
- * the caller supplies: A1 = A R_s^{-1}, G1 = A1^T A1 = R2^T R2, Q = A1 R2^{-1},
- * R = R2 R_s.  rpCholesky-QR is this algorithm with R_s from the sketch; here
+ * the caller supplies: A1 = A R_s^{-1}, G1 = A1^T A1 = R2^T R2, Q = A1 R2^{-1}
+ * (by row-wise substitution with R2, since a caller's R_s puts no bound on
+ * kappa(A1)), R = R2 R_s.  With R_s = I this is Algorithm "Basic Cholesky-QR"
+ * (Section 2.1).  rpCholesky-QR is this algorithm with R_s from the sketch; here
  * R_s is used exactly as given (no sign change, no check of its diagonal: a
  * singular or badly conditioned R_s shows up as RPCHOLQR_INFO_ECHOL).
  *   Rs, ldrs    n x n upper triangular, column-major, ldrs >= n (device, read

@@ -1,0 +1,533 @@
+// Kernels for 128 < n <= 512 (Algorithm rpCholesky-QR lines 2-3 and Algorithm
+// Preconditioned Cholesky-QR lines 2, 4 and 6), FP64.  Column counts are
+// padded to nmax, a multiple of 128 (identity beyond n in every triangle).
+//
+// Sketch QR (line 3), in 32-column panels with the arithmetic of the unblocked
+// sweep, so that R_s is the same to the bit:
+//   k_sketch_panel:  one workgroup runs Householder steps c0 .. c0+31 on the
+//                    panel's columns (each 16-lane group one column in
+//                    registers, one barrier per step), keeps reflector v_k in
+//                    place of sample column k (zero above row k) and tau_k, and
+//                    records R(k, j) for the panel's columns;
+//   k_sketch_trail:  many workgroups apply reflectors c0 .. c0+31, one by one
+//                    and in order, to every later column (a 16-lane group per
+//                    column, the reflector staged in LDS), recording R(k, j).
+//   Every column thus receives reflectors 0, 1, ... in order, each as the same
+//   CR16 dot product and fma update as in the unblocked sweep.
+//   k_big_finish:    sign-normalizes R (or takes a caller's R_s as given) and
+//                    writes the row-solve operands (write_solve_operands_big).
+// Line 2 (A1 = A R_s^{-1}), k_trsm_panel, one launch per 64-column panel P:
+//   the accumulator of each 16 x 16 tile starts from A and receives, on MFMA,
+//   -A1(:, k) R_s(k, :) for k = 0 .. 64P - 1 in ascending order (the earlier
+//   panels of A1 are read back from memory); then the panel's diagonal block is
+//   solved row by row (trsm_row).  Each entry gets the fmas of the full row
+//   solve in the same order, so A1 is the same to the bit.
+// Line 4 (Gram), k_gram_big: 128 x 128 output groups x row splits on MFMA.
+// Line 6 (Q = A1 R2^{-1}), k_passB_big: product with the explicit inverse on
+//   MFMA, in place; or, with a caller's preconditioner, k_trsm_panel with R2.
+#pragma once
+
+#include "passes.h"
+#include "sketch.h"
+#include "wide.h"
+
+namespace rpq {
+
+constexpr int kBigMaxN = 512;
+constexpr int kBigBlock = 128;                 // nmax is a multiple of this
+constexpr int kPanelW = 32;                    // sketch panel width
+constexpr int kPanelThreads = 512;             // 8 waves x 4 groups = one group per panel column
+constexpr int kTrailThreads = 256;             // 16 trailing columns per workgroup
+constexpr int kBigTri = kWH * (kWH + 1) / 2;   // packed 64-triangle
+
+struct BigSketchArgs {
+  int32_t n, s;
+  int32_t c0;      // first column of the panel
+  double* As;      // s x n, ld s: sample; column k holds reflector v_k once formed
+  double* tau;     // [n]
+  double* Rg;      // n x n row-major: R of the sample as formed (before sign normalization)
+  int32_t* info;
+};
+
+// W[t] for a run-time slot t without dynamic register indexing.
+template <int RPT>
+__device__ __forceinline__ double slot_value(const double (&W)[RPT], int t) {
+  double v = 0.0;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) v = (u == t) ? W[u] : v;
+  return v;
+}
+
+// Keeps the compiler from carrying LDS values across this point (they are
+// read again after it), so that a reflector of RPT slots is not held in
+// registers next to the column.
+__device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
+
+template <int RPT>
+__global__ __launch_bounds__(kPanelThreads) void k_sketch_panel(BigSketchArgs a) {
+  __shared__ double vbuf[2][16 * RPT];
+  __shared__ double tau_s[2];
+  // bad[k & 1] = k when reflector k has a zero or non-finite norm (written in
+  // step k-1 by the wave forming reflector k, read by all after its barrier).
+  __shared__ int bad[2];
+  const int n = a.n, s = a.s, c0 = a.c0;
+  if (c0 > 0 && a.info[0] != 0) return;  // an earlier panel failed
+  if (c0 == 0 && threadIdx.x == 0) {
+    a.info[0] = 0;
+    a.info[1] = -1;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int j = c0 + 4 * wave + q;  // my column
+  const int kend = min(c0 + kPanelW, n);
+  double W[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int r = l16 + 16 * t;
+    W[t] = (j < n && r < s) ? a.As[r + (int64_t)j * s] : 0.0;
+  }
+  if (threadIdx.x < 2) bad[threadIdx.x] = -1;
+  __syncthreads();
+
+  // Reflector k from column k, run by the whole wave owning it (group qk).
+  auto reflector = [&](int k) __attribute__((always_inline)) {
+    const int buf = k & 1, qk = (k - c0) & 3;
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int r = l16 + 16 * t;
+      const double x = (r >= k) ? W[t] : 0.0;
+      p = __builtin_fma(x, x, p);
+    }
+    const int owner_lane = 16 * qk + (k & 15);
+    const double nu2 = readlane_d(row16_sum(p), owner_lane);
+    const double alpha = readlane_d(slot_value(W, k >> 4), owner_lane);
+    if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
+      if (lane == 0) bad[buf] = k;
+      return;
+    }
+    const double nu = __builtin_sqrt(nu2);
+    const double beta = (alpha >= 0.0) ? -nu : nu;
+    const double d = 1.0 / (alpha - beta);
+    const double tau = (beta - alpha) / beta;
+    if (q == qk) {
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int r = l16 + 16 * t;
+        vbuf[buf][r] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+      }
+    }
+    if (lane == 0) {
+      tau_s[buf] = tau;
+      a.tau[k] = tau;
+      a.Rg[(int64_t)k * n + k] = beta;
+    }
+  };
+
+  // Reflector k applied to my column (rows above k meet zeros of v_k).
+  auto apply = [&](int k) __attribute__((always_inline)) {
+    const int buf = k & 1;
+    const double tau = tau_s[buf];
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) p = __builtin_fma(vbuf[buf][l16 + 16 * t], W[t], p);
+    const double tt = tau * row16_sum(p);
+    lds_reload_point();
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vbuf[buf][l16 + 16 * t], W[t]);
+    if (l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = slot_value(W, k >> 4);
+  };
+
+  if (wave == 0) reflector(c0);
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    if (bad[k & 1] >= 0) break;
+    // Reflector k (in LDS since the last barrier) replaces sample column k,
+    // where the trailing-column kernel reads it: one value per thread.
+    for (int r = threadIdx.x; r < s; r += kPanelThreads) a.As[r + (int64_t)k * s] = vbuf[k & 1][r];
+    if (j > k && j < kend) apply(k);
+    if (k + 1 < kend && wave == ((k + 1 - c0) >> 2)) reflector(k + 1);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int b = bad[0] >= 0 ? bad[0] : bad[1];
+    if (b >= 0) {
+      a.info[0] = 1;  // ESKETCH
+      a.info[1] = b;
+    }
+  }
+}
+
+// Reflectors c0 .. kend-1 applied to the columns after the panel.
+template <int RPT>
+__global__ __launch_bounds__(kTrailThreads) void k_sketch_trail(BigSketchArgs a) {
+  constexpr int VPT = (16 * RPT + kTrailThreads - 1) / kTrailThreads;  // staged values per thread
+  __shared__ double vbuf[2][16 * RPT];
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int n = a.n, s = a.s, c0 = a.c0;
+  const int kend = min(c0 + kPanelW, n);
+  const int j = kend + 16 * (int)blockIdx.x + 4 * wave + q;
+  double W[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int r = l16 + 16 * t;
+    W[t] = (j < n && r < s) ? a.As[r + (int64_t)j * s] : 0.0;
+  }
+  double nv[VPT];
+  auto fetch = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = threadIdx.x + u * kTrailThreads;
+      nv[u] = (k < kend && e < s) ? a.As[e + (int64_t)k * s] : 0.0;
+    }
+  };
+  auto put = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = threadIdx.x + u * kTrailThreads;
+      if (e < 16 * RPT) vbuf[buf][e] = nv[u];
+    }
+  };
+  fetch(c0);
+  put(0);
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    const int buf = (k - c0) & 1;
+    fetch(k + 1);
+    const double tau = a.tau[k];
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) p = __builtin_fma(vbuf[buf][l16 + 16 * t], W[t], p);
+    const double tt = tau * row16_sum(p);
+    lds_reload_point();
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vbuf[buf][l16 + 16 * t], W[t]);
+    if (j < n && l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = slot_value(W, k >> 4);
+    put(buf ^ 1);  // read in step k+1, after the barrier; last read in step k-1
+    __syncthreads();
+  }
+  if (j < n) {
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int r = l16 + 16 * t;
+      if (r < s) a.As[r + (int64_t)j * s] = W[t];
+    }
+  }
+}
+
+struct BigFinishArgs {
+  int32_t n, nmax;
+  const double* Rg;        // element (k, j) at Rg[k * rs_k + j * rs_j]
+  int64_t rs_k, rs_j;
+  int32_t normalize;       // negate rows with a negative diagonal (the sketch's R)
+  int32_t init_info;       // first kernel of the call: write info = OK
+  double* Rs;              // out: n x n column-major
+  double* Rs_out;          // optional copy
+  double* tri;             // out: packed diagonal 64-blocks
+  double* full;            // out: nmax x nmax row-major
+  int32_t* info;
+};
+
+__global__ __launch_bounds__(1024) void k_big_finish(BigFinishArgs a) {
+  if (a.init_info) {
+    if (threadIdx.x == 0) {
+      a.info[0] = 0;
+      a.info[1] = -1;
+    }
+  } else if (a.info[0] != 0) {
+    return;
+  }
+  const int n = a.n;
+  auto rn = [&](int k, int j) -> double {
+    const double v = a.Rg[k * a.rs_k + j * a.rs_j];
+    return (a.normalize && a.Rg[k * a.rs_k + k * a.rs_j] < 0.0) ? -v : v;
+  };
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    const double v = (i <= j) ? rn(i, j) : 0.0;
+    a.Rs[e] = v;
+    if (a.Rs_out) a.Rs_out[e] = v;
+  }
+  write_solve_operands_big(a.tri, a.full, n, a.nmax, rn);
+}
+
+// Line 2 for column panel P (columns 64P .. 64P+63).  With W == A it runs in
+// place (the solve Q = A1 R2^{-1}): a panel reads its own columns of A and
+// the earlier panels of the result only.
+struct BigTrsmArgs {
+  int64_t m;
+  int32_t n, nmax, P;
+  const double* A;
+  int64_t lda;
+  double* W;
+  int64_t ldw;
+  const double* tri;   // packed diagonal 64-blocks of U
+  const double* full;  // U row-major nmax x nmax
+  const int32_t* info;
+};
+
+__global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
+  __shared__ double rq[2][kWH * kR12Ld];  // U(64Q .., 64P ..) blocks, double buffered
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int P = a.P, c0 = kWH * P;
+  const int ncols = min(kWH, a.n - c0);
+  const int64_t panels = (a.m + kWave - 1) / kWave;
+  const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+  for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
+    const int64_t r0 = (pg * kPassWaves + wave) * kWave;
+    const bool valid = r0 + lane < a.m;
+    d4 acc[4][4];
+    {
+      int nc = ncols;
+      int64_t lda = a.lda;
+      asm volatile("" : "+s"(nc), "+s"(lda));
+      const double* Ap = a.A + (int64_t)c0 * lda;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int64_t row = r0 + 16 * rb + i16;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * cb + 4 * v + g;
+            acc[rb][cb][v] = (row < a.m && col < nc) ? Ap[row + (int64_t)col * lda] : 0.0;
+          }
+      }
+    }
+    __syncthreads();  // the previous panel group's readers of rq are done
+    for (int Qb = 0; Qb < P; ++Qb) {
+      const int buf = Qb & 1;
+      const double* src = a.full + (int64_t)(kWH * Qb) * a.nmax + c0;
+      for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads)
+        rq[buf][(e / kWH) * kR12Ld + e % kWH] = src[(int64_t)(e / kWH) * a.nmax + e % kWH];
+      __syncthreads();
+      const double* X = a.W + (int64_t)(kWH * Qb) * a.ldw;
+#pragma unroll 2
+      for (int kc = 0; kc < 16; ++kc) {
+        double b[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          const int64_t row = r0 + 16 * rb + i16;
+          b[rb] = (row < a.m) ? -X[row + (int64_t)(4 * kc + g) * a.ldw] : 0.0;
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const double u = rq[buf][(4 * kc + g) * kR12Ld + 16 * cb + i16];
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][cb], 0, 0, 0);
+        }
+      }
+    }
+    double vals[4][16];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vals[rb][4 * cb + v] = acc[rb][cb][v];
+    transpose_sets(vals);
+    double t[kWH];
+#pragma unroll
+    for (int col = 0; col < kWH; ++col) t[col] = vals[col & 3][4 * (col >> 4) + ((col >> 2) & 3)];
+    pin_values(t);
+    trsm_row<kWH, kTriGroup, kTriSync>(t, opaque(as_const(a.tri + (int64_t)P * kBigTri)));
+    pin_values(t);
+    store_half(a.W + (int64_t)c0 * a.ldw, a.ldw, t, r0, lane, valid, ncols);
+  }
+}
+
+// Line 4: partial Gram matrices of X (m x n, n <= nmax).  Workgroup b takes
+// output group gi = b mod ngroups, a pair (I, J), I <= J, of 128-column blocks
+// (the 64 upper 16 x 16 tiles of G(I, J), or the 36 upper ones when I == J),
+// and row split b / ngroups: 32-row blocks split, split + nsplit, ...  The two
+// column strips of a block are staged in LDS; wave w owns tile rows {2w, 2w+1}
+// (or {w, 7-w} when I == J).  Partial `split` holds every upper tile of the
+// Gram matrix in the order the Cholesky kernel reads (row-major over the upper
+// 16 x 16 block triangle).
+struct BigGramArgs {
+  int64_t m;
+  int32_t n, nmax, ngroups, nsplit;
+  const double* X;
+  int64_t ldx;
+  double* partials;
+  int64_t E;
+  const int32_t* info;
+};
+
+constexpr int kGRows = 32;
+constexpr int kGLd = 2 * kBigBlock + 4;  // LDS row stride of the staged strips
+
+template <bool DIAG, int WV>
+__device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int J, int split, double* xs) {
+  constexpr int NTW = DIAG ? 9 : 16;  // tiles of this wave
+  // tile rows of this wave and the first tile column of each
+  constexpr int B0 = DIAG ? WV : 2 * WV, B1 = DIAG ? 7 - WV : 2 * WV + 1;
+  constexpr int C0 = DIAG ? B0 : 0, C1 = DIAG ? B1 : 0;
+  constexpr int N0 = 8 - C0;  // tiles in row B0
+  static_assert(N0 + (8 - C1) == NTW, "tile count");
+  const int lane = threadIdx.x & (kWave - 1);
+  const int rq = lane >> 4, cq = lane & 15;
+  const int joff = DIAG ? 0 : kBigBlock;  // column offset of the J strip in LDS
+  d4 acc[NTW];
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int STRIP = DIAG ? kBigBlock : 2 * kBigBlock;
+  constexpr int U = kGRows * STRIP / kPassThreads;  // staged values per thread
+  const int64_t blocks = (a.m + kGRows - 1) / kGRows;
+  const int nsplit = a.nsplit;
+  double nx[U];
+  auto fetch = [&](int64_t blk) __attribute__((always_inline)) {
+    const int64_t r0 = (blk < blocks ? blk : 0) * kGRows;
+    int n = a.n;
+    asm volatile("" : "+s"(n));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kPassThreads;
+      const int r = e % kGRows, c = e / kGRows;
+      const int col = (c < kBigBlock) ? kBigBlock * I + c : kBigBlock * J + c - kBigBlock;
+      nx[u] = (blk < blocks && r0 + r < a.m && col < n) ? a.X[r0 + r + (int64_t)col * a.ldx] : 0.0;
+    }
+  };
+  fetch(split);
+  for (int64_t blk = split; blk < blocks; blk += nsplit) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kPassThreads;
+      xs[(e % kGRows) * kGLd + e / kGRows] = nx[u];
+    }
+    __syncthreads();
+    fetch(blk + nsplit);
+#pragma unroll
+    for (int qq = 0; qq < kGRows / 4; ++qq) {
+      const double* xr = xs + (4 * qq + rq) * kGLd;
+      const double a0 = xr[16 * B0 + cq], a1 = xr[16 * B1 + cq];
+      double bv[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) bv[c] = xr[joff + 16 * c + cq];
+      int tt = 0;
+#pragma unroll
+      for (int c = C0; c < 8; ++c) {
+        acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[c], acc[tt], 0, 0, 0);
+        ++tt;
+      }
+#pragma unroll
+      for (int c = C1; c < 8; ++c) {
+        acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[c], acc[tt], 0, 0, 0);
+        ++tt;
+      }
+    }
+  }
+  // Result element (i, j) of a tile sits in lane j + 16 (i mod 4), register i / 4.
+  const int NB = a.nmax / 16;
+  double* out = a.partials + (int64_t)split * a.E;
+  int tt = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int bi = 8 * I + (h == 0 ? B0 : B1);
+#pragma unroll
+    for (int c = (h == 0 ? C0 : C1); c < 8; ++c) {
+      const int bj = 8 * J + c;
+      const int tile = bi * NB - bi * (bi - 1) / 2 + (bj - bi);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)tile * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[tt][v];
+      ++tt;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
+  __shared__ double xs[kGRows * kGLd];
+  if (a.info[0] != 0) return;
+  const int gi = blockIdx.x % a.ngroups, split = blockIdx.x / a.ngroups;
+  const int NG = a.nmax / kBigBlock;
+  int I = 0, rem = gi;
+  while (rem >= NG - I) {
+    rem -= NG - I;
+    ++I;
+  }
+  const int J = I + rem;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (I == J) {
+    switch (wv) {
+      case 0: gram_big_tiles<true, 0>(a, I, J, split, xs); break;
+      case 1: gram_big_tiles<true, 1>(a, I, J, split, xs); break;
+      case 2: gram_big_tiles<true, 2>(a, I, J, split, xs); break;
+      default: gram_big_tiles<true, 3>(a, I, J, split, xs); break;
+    }
+  } else {
+    switch (wv) {
+      case 0: gram_big_tiles<false, 0>(a, I, J, split, xs); break;
+      case 1: gram_big_tiles<false, 1>(a, I, J, split, xs); break;
+      case 2: gram_big_tiles<false, 2>(a, I, J, split, xs); break;
+      default: gram_big_tiles<false, 3>(a, I, J, split, xs); break;
+    }
+  }
+}
+
+// Line 6: Q = A1 R2^{-1} with the explicit inverse T2 (nmax x nmax row-major,
+// zero outside the n x n upper triangle), in place over A1.  A workgroup takes
+// kBRows 16-row blocks at a time; wave w owns the 16-column blocks w, w + 4,
+// ... (balanced over the triangle).  All four waves read every column of the
+// rows, so the results are stored only after a barrier.  MFMA layout as in
+// k_passB: A operand T2(4 kc + l/16, 16 cb + l%16), B operand A1(row l%16,
+// 4 kc + l/16), result Q(row l%16, 16 cb + 4 v + l/16) in register v.
+constexpr int kBRows = 2;
+
+template <int NMAX>
+__global__ __launch_bounds__(kPassThreads) void k_passB_big(PassBArgs a) {
+  constexpr int NB = NMAX / 16, PERW = NB / kPassWaves;
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int nkc = (a.n + 3) / 4;
+  const int64_t groups = (a.m + 16 * kBRows - 1) / (16 * kBRows);
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const int64_t rbase = grp * 16 * kBRows;
+    d4 acc[kBRows][PERW];
+#pragma unroll
+    for (int rb = 0; rb < kBRows; ++rb)
+#pragma unroll
+      for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int col = 4 * kc + g4;
+      double b[kBRows];
+#pragma unroll
+      for (int rb = 0; rb < kBRows; ++rb) {
+        const int64_t row = rbase + 16 * rb + i16;
+        b[rb] = (row < a.m && col < a.n) ? a.Q[row + (int64_t)col * a.ldq] : 0.0;
+      }
+      const double* trow = a.T2 + (int64_t)col * NMAX + i16;
+#pragma unroll
+      for (int i = 0; i < PERW; ++i) {
+        const int cb = wave + kPassWaves * i;
+        if (cb >= (kc >> 2)) {
+          const double u = trow[16 * cb];
+#pragma unroll
+          for (int rb = 0; rb < kBRows; ++rb)
+            acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][i], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave has read these rows of A1
+#pragma unroll
+    for (int rb = 0; rb < kBRows; ++rb) {
+      const int64_t row = rbase + 16 * rb + i16;
+      if (row < a.m) {
+#pragma unroll
+        for (int i = 0; i < PERW; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * (wave + kPassWaves * i) + 4 * v + g4;
+            if (col < a.n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
+          }
+      }
+    }
+  }
+}
+
+}  // namespace rpq

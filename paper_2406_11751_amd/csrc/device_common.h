@@ -68,8 +68,10 @@ __host__ __device__ constexpr int tri_row_start(int k, int nmax) { return k * nm
 // Every thread of the block takes part.
 template <typename F>
 __device__ __forceinline__ void write_solve_operands(double* dst, int n, int nmax, F&& u) {
-  auto un = [&](int k, int j) -> double { return (k >= n || j >= n) ? ((j == k) ? 1.0 : 0.0) : u(k, j); };
-  auto put_packed = [&](double* out, int k0, int w) {  // rows k0 .. k0+w-1, columns k0 ..
+  auto un = [&](int k, int j) __attribute__((always_inline)) -> double {
+    return (k >= n || j >= n) ? ((j == k) ? 1.0 : 0.0) : u(k, j);
+  };
+  auto put_packed = [&](double* out, int k0, int w) __attribute__((always_inline)) {  // rows k0 .. k0+w-1, cols k0 ..
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
       const int k = e / w, j = e - k * w;
       if (j < k) continue;
@@ -85,6 +87,29 @@ __device__ __forceinline__ void write_solve_operands(double* dst, int n, int nma
     put_packed(dst + H * (H + 1) / 2, H, H);
     double* u12 = dst + H * (H + 1);
     for (int e = threadIdx.x; e < H * H; e += blockDim.x) u12[e] = un(e / H, H + e % H);
+  }
+}
+
+// Row-solve operands of an upper triangular U of order n > 128, padded to nmax
+// (a multiple of 64; identity beyond n): the packed triangles of the 64 x 64
+// diagonal blocks U(64p : 64p+64, 64p : 64p+64), p = 0 .. nmax/64 - 1, back to
+// back in tri (64 * 65 / 2 doubles each), and all of U row-major nmax x nmax in
+// full (zero below the diagonal), from which the off-diagonal blocks are read.
+template <typename F>
+__device__ __forceinline__ void write_solve_operands_big(double* tri, double* full, int n, int nmax, F&& u) {
+  auto un = [&](int k, int j) __attribute__((always_inline)) -> double {
+    return (k >= n || j >= n) ? ((j == k) ? 1.0 : 0.0) : u(k, j);
+  };
+  constexpr int H = 64, HT = H * (H + 1) / 2;
+  for (int e = threadIdx.x; e < (nmax / H) * H * H; e += blockDim.x) {
+    const int p = e / (H * H), k = (e / H) % H, j = e % H;
+    if (j < k) continue;
+    const int k0 = p * H;
+    tri[p * HT + tri_row_start(k, H) + (j - k)] = (j == k) ? 1.0 / un(k0 + k, k0 + k) : un(k0 + k, k0 + j);
+  }
+  for (int e = threadIdx.x; e < nmax * nmax; e += blockDim.x) {
+    const int k = e / nmax, j = e % nmax;
+    full[e] = (j >= k) ? un(k, j) : 0.0;
   }
 }
 

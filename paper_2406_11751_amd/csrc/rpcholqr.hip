@@ -20,14 +20,16 @@
 #include "sketch.h"
 #include "small.h"
 #include "wide.h"
+#include "big.h"
 #include "batched.h"
 
 namespace {
 
 using namespace rpq;
 
-constexpr int kMaxN = 128;
+constexpr int kMaxN = kBigMaxN;
 constexpr int kWideN = 128;  // column class of 64 < n <= 128 (two-half row solve, separate Gram pass)
+constexpr int kBigMaxSketchRows = 16 * 96;  // panel sketch: up to 96 sample rows per lane
 constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles in LDS
 constexpr int kPassAMaxBlocks = 512;
 static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
@@ -38,7 +40,7 @@ struct Plan {
   int64_t panels = 0;
   int PA = 0, PB = 0, G2 = 0;
   int rpt = 0;  // sample rows per lane in the register sketch QR; 0 = generic kernel
-  size_t off_tri = 0, off_tri2 = 0, off_tri3 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0, off_R1 = 0;
+  size_t off_tri = 0, off_tri2 = 0, off_tri3 = 0, off_Rs = 0, off_part = 0, off_part2 = 0, off_As = 0, off_R1 = 0, off_R2 = 0;
   size_t total = 0;
 };
 
@@ -57,7 +59,7 @@ int pick_nmax(int64_t n) {
 // the partials itself (no second-level region; the batched path, pa_cap <= 64).
 bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassAMaxBlocks,
                bool direct_partials = false, bool refine = false) {
-  if (n < 1 || m < n || s < n || n > kMaxN) return false;
+  if (n < 1 || m < n || s < n || n > kWideN) return false;
   p->nmax = pick_nmax(n);
   if (p->nmax == kWideN && refine) return false;  // refined precisions: n <= 64
   p->NB = (p->nmax + 15) / 16;
@@ -92,8 +94,69 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
   off = align256(off + (size_t)s * n * sizeof(double));
   p->off_R1 = off;  // refined precisions: R2 R_s of the first pass, n x n, ld n
   if (refine) off = align256(off + (size_t)n * n * sizeof(double));
+  p->off_R2 = off;  // R2 for the substitution form of line 6, n x n, ld n
+  off = align256(off + (size_t)n * n * sizeof(double));
   p->total = off;
   return true;
+}
+
+// Plan of the columns class 128 < n <= 512 (big.h).  nmax = 128 ceil(n/128).
+struct BigPlan {
+  int nmax = 0, NB = 0, NP = 0, rpt = 0, ngroups = 0, nsplit = 0, G2 = 0;
+  int64_t E = 0;
+  size_t off_tri = 0, off_full = 0, off_T2 = 0, off_tri3 = 0, off_full3 = 0, off_Gg = 0, off_Rs = 0, off_Rg = 0,
+         off_tau = 0, off_part = 0, off_part2 = 0, off_As = 0;
+  size_t total = 0;
+};
+
+bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap = kPassAMaxBlocks,
+                   bool refine = false) {
+  if (n <= kWideN || n > kBigMaxN || m < n || s < n || refine) return false;
+  if (s > kBigMaxSketchRows) return false;
+  p->nmax = (int)((n + kBigBlock - 1) / kBigBlock) * kBigBlock;
+  p->NB = p->nmax / 16;
+  p->NP = p->nmax / kWH;
+  p->E = (int64_t)p->NB * (p->NB + 1) / 2 * 256;
+  const int64_t rows = (s + 15) / 16;
+  p->rpt = rows <= 16 ? 16 : rows <= 24 ? 24 : rows <= 32 ? 32 : rows <= 48 ? 48 : rows <= 64 ? 64 : 96;
+  const int ng = p->nmax / kBigBlock;
+  p->ngroups = ng * (ng + 1) / 2;
+  const int64_t rblocks = (m + kGRows - 1) / kGRows;
+  int64_t ns = (1024 + p->ngroups - 1) / p->ngroups;
+  ns = std::min<int64_t>(std::min<int64_t>(ns, rblocks), std::min<int64_t>(pa_cap, kPassAMaxBlocks));
+  p->nsplit = (int)std::max<int64_t>(ns, 1);
+  p->G2 = (p->nsplit + kReduceChunk - 1) / kReduceChunk;
+  const size_t d = sizeof(double), nm = (size_t)p->nmax;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  p->off_tri = take((size_t)p->NP * kBigTri * d);
+  p->off_full = take(nm * nm * d);
+  p->off_T2 = take(nm * nm * d);
+  p->off_tri3 = take((size_t)p->NP * kBigTri * d);
+  p->off_full3 = take(nm * nm * d);
+  p->off_Gg = take(nm * (nm + 1) * d);
+  p->off_Rs = take((size_t)n * n * d);
+  p->off_Rg = take((size_t)n * n * d);
+  p->off_tau = take((size_t)n * d);
+  p->off_part = take((size_t)p->nsplit * p->E * d);
+  p->off_part2 = take((size_t)p->G2 * p->E * d);
+  p->off_As = take((size_t)s * n * d);
+  p->total = off;
+  return true;
+}
+
+// Workspace bytes for any supported size (0 if unsupported).
+size_t plan_total(int64_t m, int64_t n, int64_t s, int64_t pa_cap, bool refine) {
+  if (n > kWideN) {
+    BigPlan b;
+    return make_big_plan(m, n, s, &b, pa_cap, refine) ? b.total : 0;
+  }
+  Plan p;
+  return make_plan(m, n, s, &p, pa_cap, false, refine) ? p.total : 0;
 }
 
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -206,6 +269,208 @@ void with_nmax(int nmax, F&& fn) {
   }
 }
 
+template <typename F>
+void with_big_nmax(int nmax, F&& fn) {
+  switch (nmax) {
+    case 256: fn(std::integral_constant<int, 256>{}); break;
+    case 384: fn(std::integral_constant<int, 384>{}); break;
+    default: fn(std::integral_constant<int, 512>{}); break;
+  }
+}
+
+template <typename F>
+void with_big_rpt(int rpt, F&& fn) {
+  switch (rpt) {
+    case 16: fn(std::integral_constant<int, 16>{}); break;
+    case 24: fn(std::integral_constant<int, 24>{}); break;
+    case 32: fn(std::integral_constant<int, 32>{}); break;
+    case 48: fn(std::integral_constant<int, 48>{}); break;
+    case 64: fn(std::integral_constant<int, 64>{}); break;
+    default: fn(std::integral_constant<int, 96>{}); break;
+  }
+}
+
+// The 128 < n <= 512 class (big.h); arguments as factor_impl, already checked
+// for sizes, pointers and precision.
+int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda, double* Q,
+                   int64_t ldq, double* R, int64_t ldr, int32_t precision, void* ws, size_t ws_bytes,
+                   rpcholqr_info* info, void* stream, int64_t* idx, double* As, double* Rs, double* A1, double* G1,
+                   double* R2, const double* Rs_in, int64_t ldrs, int64_t pa_cap, bool timed) {
+  BigPlan p;
+  if (!make_big_plan(m, n, s, &p, pa_cap, precision != RPCHOLQR_FP64)) return RPCHOLQR_EUNSUPPORTED;
+  const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
+  if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
+    return RPCHOLQR_EINVAL;
+  if (!ws || ws_bytes < p.total || ((uintptr_t)ws & 255)) return RPCHOLQR_EWORKSPACE;
+  if (overlaps(ws, p.total, A, a_bytes) || overlaps(ws, p.total, Q, q_bytes) || overlaps(ws, p.total, R, r_bytes))
+    return RPCHOLQR_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  auto at_ws = [&](size_t off) { return (double*)(base + off); };
+  int32_t* inf = (int32_t*)info;
+  hipEvent_t* ev = timed ? timing_slot() : nullptr;
+  int stage = 0;
+  auto mark = [&]() {
+    if (ev) (void)hipEventRecord(ev[stage++], st);
+  };
+  auto launched = [&]() { return hipGetLastError() == hipSuccess; };
+  mark();
+
+  // Lines 2-3: sample and gather, then the panel sketch QR, then R_s and the
+  // row-solve operands.  With Rs_in the finishing kernel takes the caller's R_s.
+  BigFinishArgs fa{};
+  fa.n = (int32_t)n;
+  fa.nmax = p.nmax;
+  fa.Rs = at_ws(p.off_Rs);
+  fa.Rs_out = Rs;
+  fa.tri = at_ws(p.off_tri);
+  fa.full = at_ws(p.off_full);
+  fa.info = inf;
+  if (Rs_in) {
+    fa.Rg = Rs_in;
+    fa.rs_k = 1;
+    fa.rs_j = ldrs;
+    fa.normalize = 0;
+    fa.init_info = 1;
+  } else {
+    SketchArgs sa{};
+    sa.m = m;
+    sa.n = (int32_t)n;
+    sa.s = (int32_t)s;
+    sa.seed = seed;
+    sa.scale = std::sqrt((double)m / (double)s);
+    sa.A = A;
+    sa.lda = lda;
+    sa.As = at_ws(p.off_As);
+    sa.info = inf;
+    sa.idx_out = idx;
+    sa.As_out = As;
+    const int64_t gather_blocks = (s * n + kGatherThreads - 1) / kGatherThreads;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
+    if (!launched()) return RPCHOLQR_EHIP;
+    BigSketchArgs ba{};
+    ba.n = (int32_t)n;
+    ba.s = (int32_t)s;
+    ba.As = at_ws(p.off_As);
+    ba.tau = at_ws(p.off_tau);
+    ba.Rg = at_ws(p.off_Rg);
+    ba.info = inf;
+    with_big_rpt(p.rpt, [&](auto rp) {
+      constexpr int RPT = decltype(rp)::value;
+      for (int c0 = 0; c0 < n; c0 += kPanelW) {
+        ba.c0 = c0;
+        hipLaunchKernelGGL((k_sketch_panel<RPT>), dim3(1), dim3(kPanelThreads), 0, st, ba);
+        const int64_t trail = n - std::min<int64_t>(c0 + kPanelW, n);
+        if (trail > 0)
+          hipLaunchKernelGGL((k_sketch_trail<RPT>), dim3((unsigned)((trail + 15) / 16)), dim3(kTrailThreads), 0, st,
+                             ba);
+      }
+    });
+    fa.Rg = at_ws(p.off_Rg);
+    fa.rs_k = n;
+    fa.rs_j = 1;
+    fa.normalize = 1;
+    fa.init_info = 0;
+  }
+  hipLaunchKernelGGL(k_big_finish, dim3(1), dim3(1024), 0, st, fa);
+  if (!launched()) return RPCHOLQR_EHIP;
+  mark();
+
+  // Line 2 (A1 = A R_s^{-1} into Q, one launch per 64-column panel) and line 4 (Gram partials).
+  const int cus = std::max(device_cus(), 1);
+  const int64_t pgroups = ((m + kWave - 1) / kWave + kPassWaves - 1) / kPassWaves;
+  const unsigned trsm_grid = (unsigned)std::min<int64_t>(pgroups, 2 * cus);
+  auto trsm = [&](const double* src, int64_t ldsrc, const double* tri, const double* full) {
+    BigTrsmArgs ta{};
+    ta.m = m;
+    ta.n = (int32_t)n;
+    ta.nmax = p.nmax;
+    ta.A = src;
+    ta.lda = ldsrc;
+    ta.W = Q;
+    ta.ldw = ldq;
+    ta.tri = tri;
+    ta.full = full;
+    ta.info = inf;
+    for (int P = 0; P * kWH < n; ++P) {
+      ta.P = P;
+      hipLaunchKernelGGL(k_trsm_panel, dim3(trsm_grid), dim3(kPassThreads), 0, st, ta);
+    }
+  };
+  trsm(A, lda, at_ws(p.off_tri), at_ws(p.off_full));
+  BigGramArgs ga{};
+  ga.m = m;
+  ga.n = (int32_t)n;
+  ga.nmax = p.nmax;
+  ga.ngroups = p.ngroups;
+  ga.nsplit = p.nsplit;
+  ga.X = Q;
+  ga.ldx = ldq;
+  ga.partials = at_ws(p.off_part);
+  ga.E = p.E;
+  ga.info = inf;
+  hipLaunchKernelGGL(k_gram_big, dim3((unsigned)(p.ngroups * p.nsplit)), dim3(kPassThreads), 0, st, ga);
+  if (!launched()) return RPCHOLQR_EHIP;
+  mark();
+  if (A1 && hipMemcpy2DAsync(A1, (size_t)m * sizeof(double), Q, (size_t)ldq * sizeof(double),
+                             (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return RPCHOLQR_EHIP;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((p.E + kReduceThreads - 1) / kReduceThreads), p.G2),
+                     dim3(kReduceThreads), 0, st, (const double*)at_ws(p.off_part), p.nsplit, (int)p.E,
+                     at_ws(p.off_part2), (const int32_t*)inf);
+  if (!launched()) return RPCHOLQR_EHIP;
+  mark();
+
+  // Lines 5 (Cholesky, R2^{-1}) and 8 (R = R2 R_s).
+  const bool substitute = Rs_in != nullptr;
+  CholArgs ca{};
+  ca.partial2 = at_ws(p.off_part2);
+  ca.G2 = p.G2;
+  ca.E = (int32_t)p.E;
+  ca.NB = p.NB;
+  ca.n = (int32_t)n;
+  ca.nmax = p.nmax;
+  ca.Rs = at_ws(p.off_Rs);
+  ca.T2 = at_ws(p.off_T2);
+  ca.R = R;
+  ca.ldr = ldr;
+  ca.info = inf;
+  ca.G1_out = G1;
+  ca.R2_out = R2;
+  ca.fail_code = RPCHOLQR_INFO_ECHOL;
+  if (substitute) ca.R2_out = at_ws(p.off_Rg);  // R2, n x n (the sketch's R is no longer needed)
+  ca.Gg = at_ws(p.off_Gg);
+  with_big_nmax(p.nmax, [&](auto nm) {
+    hipLaunchKernelGGL((k_cholesky<decltype(nm)::value>), dim3(1), dim3(kCholThreads), 0, st, ca);
+  });
+  if (!launched()) return RPCHOLQR_EHIP;
+  mark();
+
+  // Line 6: Q = A1 R2^{-1} in place (explicit inverse), or by substitution with
+  // a caller's preconditioner (see factor_impl).
+  if (substitute) {
+    hipLaunchKernelGGL(k_solve_operands, dim3(1), dim3(kCholThreads), 0, st, (const double*)at_ws(p.off_Rg), (int)n,
+                       p.nmax, at_ws(p.off_tri3), at_ws(p.off_full3), (const int32_t*)inf);
+    trsm(Q, ldq, at_ws(p.off_tri3), at_ws(p.off_full3));
+  } else {
+    PassBArgs pb{};
+    pb.m = m;
+    pb.n = (int32_t)n;
+    pb.T2 = at_ws(p.off_T2);
+    pb.Q = Q;
+    pb.ldq = ldq;
+    pb.info = inf;
+    const int64_t groups = (m + 16 * kBRows - 1) / (16 * kBRows);
+    const unsigned grid = (unsigned)std::min<int64_t>(groups, 4 * cus);
+    with_big_nmax(p.nmax, [&](auto nm) {
+      hipLaunchKernelGGL((k_passB_big<decltype(nm)::value>), dim3(grid), dim3(kPassThreads), 0, st, pb);
+    });
+  }
+  if (!launched()) return RPCHOLQR_EHIP;
+  mark();
+  return RPCHOLQR_OK;
+}
+
 // With Rs_in (n x n upper triangular, ld ldrs) the sketch is skipped and R_s is
 // taken as given (Algorithm Preconditioned Cholesky-QR); s is then n.
 int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
@@ -219,6 +484,9 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
   const bool refine = precision == RPCHOLQR_FP32_REFINE || precision == RPCHOLQR_BF16X2_REFINE;
   if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
+  if (n > kWideN)
+    return factor_big(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, ws, ws_bytes, info, stream, idx, As, Rs,
+                      A1, G1, R2, Rs_in, ldrs, pa_cap, timed);
   Plan p;
   if (!make_plan(m, n, s, &p, pa_cap, false, refine)) return RPCHOLQR_EUNSUPPORTED;
   const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
@@ -334,7 +602,8 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   // kappa(R2) (Theorem t_perturb1); with the sketch's R_s, kappa(A1) is small
   // (Lemma l_31) and the product with the explicit R2^{-1} is used.
   const bool substitute = Rs_in != nullptr;
-  ca.tri_out = substitute ? tri3 : nullptr;
+  double* R2s = (double*)(base + p.off_R2);
+  if (substitute) ca.R2_out = R2s;  // R2, n x n, for the row-solve operands
   auto cholesky = [&](const CholArgs& c) {
     if (p.nmax == kWideN) {
       hipLaunchKernelGGL((k_cholesky<kWideN>), dim3(1), dim3(kCholThreads), 0, st, c);
@@ -364,6 +633,8 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
       with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
   };
   if (substitute) {
+    hipLaunchKernelGGL(k_solve_operands, dim3(1), dim3(kCholThreads), 0, st, (const double*)R2s, (int)n, p.nmax, tri3,
+                       (double*)nullptr, (const int32_t*)inf);
     PassAArgs ps = pa;
     ps.A = Q;
     ps.lda = ldq;
@@ -437,9 +708,9 @@ void* scratch_address() {
 // whose workspace fits the scratch array, or 0 if none does.
 int64_t noalloc_pa_cap(int64_t m, int64_t n, int64_t s, bool refine) {
   for (int64_t cap = kPassAMaxBlocks; cap >= 1; cap /= 2) {
-    Plan p;
-    if (!make_plan(m, n, s, &p, cap, false, refine)) return -1;
-    if (p.total <= kScratchBytes) return cap;
+    const size_t total = plan_total(m, n, s, cap, refine);
+    if (total == 0) return -1;
+    if (total <= kScratchBytes) return cap;
   }
   return 0;
 }
@@ -769,9 +1040,7 @@ int32_t rpcholqr_max_n(void) { return kMaxN; }
 size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision) {
   if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
     return 0;
-  Plan p;
-  if (!make_plan(m, n, s, &p, kPassAMaxBlocks, false, precision != RPCHOLQR_FP64)) return 0;
-  return p.total;
+  return plan_total(m, n, s, kPassAMaxBlocks, precision != RPCHOLQR_FP64);
 }
 
 int32_t rpcholqr_factor(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,

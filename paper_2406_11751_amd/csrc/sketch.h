@@ -102,7 +102,7 @@ __device__ __forceinline__ void sketch_finish(const SketchArgs& a, const double*
     if (a.Rs_out) a.Rs_out[e] = v;
   }
   // element (k, j) of the sign-normalized R
-  write_solve_operands(a.tri, n, nmax, [&](int k, int j) -> double {
+  write_solve_operands(a.tri, n, nmax, [&](int k, int j) __attribute__((always_inline)) -> double {
     const double rkk = Rl[k * LDR + k];
     const double v = Rl[k * LDR + j];
     return (NORMALIZE && rkk < 0.0) ? -v : v;

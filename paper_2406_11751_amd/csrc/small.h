@@ -47,8 +47,7 @@ struct CholArgs {
   double* G1_out;       // optional n x n, ld n (upper triangle)
   double* R2_out;       // optional n x n, ld n
   int32_t fail_code;    // info code for a failed pivot (ECHOL, or ECHOL2 in a second pass)
-  double* tri_out;      // optional: R2 as row-solve operands (write_solve_operands), for a
-                        // substitution Q = A1 R2^{-1}
+  double* Gg;           // nmax > 128: G1, then R2, nmax x (nmax + 1) row-major (workspace)
 };
 
 // Blocked Cholesky G1 = R2^T R2 with R2^{-1} and R = R2 R_s, one workgroup of
@@ -102,25 +101,28 @@ __device__ __forceinline__ void store_d(double* M, int ld, int r0, int c0, int l
 // NMAX <= 64: G, R2^{-1} and R_s all staged in LDS.  NMAX = 128: only G (then
 // R2) fits in LDS; R2^{-1} is built directly in the T2 output (global memory,
 // row-major, visible to the workgroup after each barrier) and R_s is read from
-// its column-major workspace copy.
+// its column-major workspace copy.  NMAX > 128: G as well lives in global
+// memory (the workspace copy a.Gg), with the same operations in the same order.
 template <int NMAX>
 __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
   constexpr int NB = NMAX / 16;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int E = NT * 256;
   constexpr bool WIDE = NMAX > kCholMaxN;
-  constexpr int LD = NMAX + 1;               // LDS row stride
+  constexpr bool GLOBAL_G = NMAX > 2 * kCholMaxN;
+  constexpr int LD = NMAX + 1;               // row stride of G
   constexpr int TLD = WIDE ? NMAX : LD;      // row stride of R2^{-1}
   constexpr int PER = (E + kCholThreads - 1) / kCholThreads;  // Gram entries per thread
   constexpr int PCH_MAX = WIDE ? 5 : 10;                      // registers: PCH x kMaxPartial2 loads
   constexpr int PCH = PER < PCH_MAX ? PER : PCH_MAX;          // entries per assembly round
-  static_assert(NMAX % 16 == 0 && (NMAX <= kCholMaxN || NMAX == 2 * kCholMaxN), "block size");
-  __shared__ double Gs[NMAX * LD];                // G1, then R2 (upper)
+  static_assert(NMAX % 16 == 0 && (NMAX <= kCholMaxN || NMAX % (2 * kCholMaxN) == 0), "block size");
+  __shared__ double Gsl[GLOBAL_G ? 1 : NMAX * LD];  // G1, then R2 (upper)
   __shared__ double Tsl[WIDE ? 1 : NMAX * LD];    // R2^{-1} (upper), NMAX <= 64
   __shared__ double Rsl[WIDE ? 1 : NMAX * LD];    // R_s, NMAX <= 64
   __shared__ int bad_s;
   if (a.info[0] != 0) return;
   double* Ts = WIDE ? a.T2 : Tsl;
+  double* Gs = GLOBAL_G ? a.Gg : Gsl;
   const int n = a.n, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   if (tid == 0) bad_s = -1;
 
@@ -313,7 +315,6 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
       a.R2_out[e] = (i <= j) ? Gs[i * LD + j] : 0.0;
     }
   }
-  if (a.tri_out) write_solve_operands(a.tri_out, n, NMAX, [&](int k, int j) -> double { return Gs[k * LD + j]; });
   // T2 for pass B: NMAX x NMAX row-major, zero outside the n x n upper triangle.
   if constexpr (!WIDE) {
     for (int e = tid; e < NMAX * NMAX; e += kCholThreads) {
@@ -359,6 +360,19 @@ __device__ __forceinline__ void cholesky_body(const CholArgs& a) {
       if (i / 16 > j / 16) a.R[i + (int64_t)j * a.ldr] = 0.0;
     }
   }
+}
+
+// Row-solve operands (write_solve_operands, or write_solve_operands_big for
+// nmax > 128 with the full matrix in `full`) of the n x n upper triangular U
+// (column-major, ld n), for the substitution form of line 6 with U = R2.
+__global__ __launch_bounds__(kCholThreads) void k_solve_operands(const double* U, int n, int nmax, double* tri,
+                                                                 double* full, const int32_t* info) {
+  if (info[0] != 0) return;
+  auto u = [U, n](int k, int j) __attribute__((always_inline)) -> double { return U[k + (int64_t)j * n]; };
+  if (nmax > 2 * kCholMaxN)
+    write_solve_operands_big(tri, full, n, nmax, u);
+  else
+    write_solve_operands(tri, n, nmax, u);
 }
 
 template <int NMAX>

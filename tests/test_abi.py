@@ -53,12 +53,19 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100_000, 32, 1536) > rq.workspace_bytes(100_000, 32, 96)
     assert rq.workspace_bytes(100_000, 32, 1537) == 0  # beyond the largest supported sample
     # 64 < n <= 128: FP64 only; the generic sketch kernel bounds s
-    assert rq.max_n() == 128
+    assert rq.max_n() == 512
     assert rq.workspace_bytes(100_000, 128, 384) >= 384 * 128 * 8 + 128 * 128 * 8
     assert rq.workspace_bytes(100_000, 65, 1536) > 0
     assert rq.workspace_bytes(100_000, 65, 1537) == 0
     assert rq.workspace_bytes(100_000, 100, 300, precision=rq.FP32_REFINE) == 0
     assert rq.workspace_bytes(100_000, 64, 192, precision=rq.FP32_REFINE) > 0
+    # 128 < n <= 512: the panel sketch takes s <= 1536; columns padded to 128k
+    for n in (129, 256, 300, 512):
+        assert rq.workspace_bytes(1_000_000, n, 3 * n) >= 3 * n * n * 8
+    assert rq.workspace_bytes(1_000_000, 512, 1536) > rq.workspace_bytes(1_000_000, 256, 768)
+    assert rq.workspace_bytes(1_000_000, 300, 1537) == 0
+    assert rq.workspace_bytes(100, 129, 387) == 0       # m < n
+    assert rq.workspace_bytes(1_000_000, 513, 1539) == 0
 
 
 def test_missing_library_fails_loudly(monkeypatch):

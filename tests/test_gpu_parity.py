@@ -112,6 +112,34 @@ WIDE_CASES = [
 ]
 
 
+# 128 < n <= 512: the panel sketch (32-column panels, reflectors applied column
+# by column to the later panels), the MFMA row-panel solve (64-column panels,
+# earlier panels of A1 read back), the 128 x 128 Gram groups, the Cholesky with
+# G in global memory and the MFMA pass B.  Ragged n (129, 200, 300), every
+# padded width (256, 384, 512), every sketch rows-per-lane class (32 .. 96),
+# the largest s, a single row-panel group, s = 2n.
+BIG_CASES = [
+    (3000, 129, 387, 1e8, 30),
+    (20001, 200, 600, 1e12, 31),
+    (12000, 256, 768, 1e15, 32),
+    (5000, 300, 900, 1e6, 33),
+    (4000, 384, 1152, 1e10, 34),
+    (6000, 512, 1536, 1e10, 35),
+    (40000, 256, 512, 1e5, 36),     # s = 2n
+    (1000, 140, 1536, 1e3, 37),     # largest s, few rows
+    (230, 130, 390, 1e4, 38),       # a single row-panel group
+    (3001, 160, 260, 1e9, 39),      # s in 257..384 (24 rows per lane)
+]
+
+
+@pytest.mark.parametrize("m,n,s,kappa,seed", BIG_CASES)
+def test_parity_big(m, n, s, kappa, seed):
+    A_h = gen_usv(m, n, kappa, 100 + seed)
+    _, _, orth, res = check_case(A_h, s, seed)
+    assert orth < (1e-12 if s >= 2 * n else 1e-10)
+    assert res < 1e-15
+
+
 @pytest.mark.parametrize("m,n,s,kappa,seed", CASES)
 def test_parity_small(m, n, s, kappa, seed):
     A_h = gen_usv(m, n, kappa, 100 + seed)
@@ -207,7 +235,7 @@ def test_leading_dimensions(pad, off, n):
     assert metrics.rel_fro(host(Q), ref.Q) < TOL and metrics.rel_fro(host(R), ref.R) < TOL
 
 
-@pytest.mark.parametrize("n,col", [(12, 7), (100, 90)])
+@pytest.mark.parametrize("n,col", [(12, 7), (100, 90), (300, 250)])
 def test_esketch_zero_column(n, col):
     A_h = gen_usv(2000, n, 1e3, 1)
     A_h[:, col] = 0.0
@@ -223,7 +251,8 @@ def test_esketch_zero_column(n, col):
 # sketch), where a sweep that went on would report it instead.  s = 400 takes
 # the generic sketch kernel.
 @pytest.mark.parametrize("n,s,cols", [(24, 72, (3, 17)), (40, 120, (17, 33)), (24, 400, (3, 17)),
-                                      (100, 300, (3, 17)), (100, 300, (65, 81)), (100, 300, (33, 99))])
+                                      (100, 300, (3, 17)), (100, 300, (65, 81)), (100, 300, (33, 99)),
+                                      (200, 400, (3, 17)), (200, 400, (40, 150))])
 def test_esketch_first_of_two_zero_columns(n, s, cols):
     A_h = gen_usv(3000, n, 1e3, 5)
     for c in cols:
@@ -236,7 +265,7 @@ def test_esketch_first_of_two_zero_columns(n, s, cols):
     assert e.value.code == 1 and e.value.index == cols[0]
 
 
-@pytest.mark.parametrize("n,col", [(12, 3), (80, 70)])
+@pytest.mark.parametrize("n,col", [(12, 3), (80, 70), (260, 200)])
 def test_echol_nonfinite_unsampled_row(n, col):
     m, s = 2000, 3 * n
     A_h = gen_usv(m, n, 1e3, 2)

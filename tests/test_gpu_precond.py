@@ -37,7 +37,8 @@ def announce(*args):
 
 
 @pytest.mark.parametrize("m,n,s,kappa,seed", [(5000, 24, 72, 1e8, 1), (20000, 64, 192, 1e12, 2),
-                                              (3001, 100, 300, 1e10, 3), (1000, 128, 384, 1e6, 4)])
+                                              (3001, 100, 300, 1e10, 3), (1000, 128, 384, 1e6, 4),
+                                              (4000, 300, 900, 1e12, 5)])
 def test_sketch_preconditioner_reproduces_factor(m, n, s, kappa, seed):
     # Given the sketch's own R_s, Algorithm 1 is the rest of rpCholesky-QR: the
     # same A1, G1, R2 and R to the bit.  Line 6 differs in method (substitution
@@ -53,7 +54,8 @@ def test_sketch_preconditioner_reproduces_factor(m, n, s, kappa, seed):
     assert metrics.rel_fro(host(Q2), ref.Q) < TOL and metrics.rel_fro(host(R2), ref.R) < TOL
 
 
-@pytest.mark.parametrize("m,n,kappa,seed", [(4000, 16, 1e6, 5), (10000, 50, 1e8, 6), (2500, 96, 1e10, 7)])
+@pytest.mark.parametrize("m,n,kappa,seed", [(4000, 16, 1e6, 5), (10000, 50, 1e8, 6), (2500, 96, 1e10, 7),
+                                            (3000, 200, 1e10, 8)])
 def test_against_oracle_alg1_with_signed_preconditioner(m, n, kappa, seed):
     # A preconditioner that is not sign-normalized: the sketch's R_s with every
     # third row negated (Algorithm 1 takes any nonsingular upper triangular R_s).
@@ -77,7 +79,7 @@ def test_against_oracle_alg1_with_signed_preconditioner(m, n, kappa, seed):
 U64 = 2.0 ** -53
 
 
-@pytest.mark.parametrize("n", [16, 64, 100])
+@pytest.mark.parametrize("n", [16, 64, 100, 160])
 def test_basic_cholqr_loses_orthogonality_as_kappa_squared(n):
     m, kappa = 20000, 1e3
     A_h = gen_usv(m, n, kappa, 11)

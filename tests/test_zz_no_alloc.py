@@ -2,7 +2,8 @@
 workspace in a static device array) against rpcholqr_factor with a caller's
 workspace, called through the C ABI: several calls in a row on the one array,
 each later one smaller than the one before, so that a call that depended on the
-array's leftover contents would show."""
+array's leftover contents would show.  The first (n = 300) needs fewer Gram
+partials to fit the array, so it agrees to rounding rather than to the bit."""
 import ctypes
 
 import numpy as np
@@ -68,8 +69,8 @@ def no_alloc(A, s, seed, prec):
 
 # (m, n, s, kappa, precision): decreasing sizes; the 128-column class, the
 # 64-column class, a refined precision and a small ragged case.
-CALLS = [(400_000, 100, 300, 1e10, 0), (300_001, 64, 192, 1e12, 0), (100_003, 48, 144, 1e8, 1),
-         (5_000, 24, 72, 1e6, 0)]
+CALLS = [(60_000, 300, 900, 1e10, 0), (400_000, 100, 300, 1e10, 0), (300_001, 64, 192, 1e12, 0),
+         (100_003, 48, 144, 1e8, 1), (5_000, 24, 72, 1e6, 0)]
 
 
 def test_no_alloc_matches_workspace_entry_point():
@@ -80,8 +81,8 @@ def test_no_alloc_matches_workspace_entry_point():
         Qn, Rn = no_alloc(A, s, 9 + i, prec)
         assert metrics.rel_fro(Qn.cpu().numpy(), Qw.cpu().numpy()) < TOL
         assert metrics.rel_fro(Rn.cpu().numpy(), Rw.cpu().numpy()) < TOL
-        # these sizes fit the array with the usual partial count: the same bits
-        assert torch.equal(Qn, Qw) and torch.equal(Rn, Rw)
+        if n <= 128:  # these fit the array with the usual partial count: the same bits
+            assert torch.equal(Qn, Qw) and torch.equal(Rn, Rw)
         assert metrics.orth_error(Qn) < 1e-12
 
 
