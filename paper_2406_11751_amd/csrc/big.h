@@ -2,14 +2,14 @@
 // Preconditioned Cholesky-QR lines 2, 4 and 6), FP64.  Column counts are
 // padded to nmax, a multiple of 128 (identity beyond n in every triangle).
 //
-// Sketch QR (line 3), in 32-column panels with the arithmetic of the unblocked
-// sweep, so that R_s is the same to the bit:
-//   k_sketch_panel:  one workgroup runs Householder steps c0 .. c0+31 on the
+// Sketch QR (line 3), in panels of 32 (or 16) columns with the arithmetic of
+// the unblocked sweep, so that R_s is the same to the bit:
+//   k_sketch_panel:  one workgroup runs Householder steps c0 .. c0+pw-1 on the
 //                    panel's columns (each 16-lane group one column in
 //                    registers, one barrier per step), keeps reflector v_k in
 //                    place of sample column k (zero above row k) and tau_k, and
 //                    records R(k, j) for the panel's columns;
-//   k_sketch_trail:  many workgroups apply reflectors c0 .. c0+31, one by one
+//   k_sketch_trail:  many workgroups apply reflectors c0 .. c0+pw-1, one by one
 //                    and in order, to every later column (a 16-lane group per
 //                    column, the reflector staged in LDS), recording R(k, j).
 //   Every column thus receives reflectors 0, 1, ... in order, each as the same
@@ -35,14 +35,18 @@ namespace rpq {
 
 constexpr int kBigMaxN = 512;
 constexpr int kBigBlock = 128;                 // nmax is a multiple of this
-constexpr int kPanelW = 32;                    // sketch panel width
-constexpr int kPanelThreads = 512;             // 8 waves x 4 groups = one group per panel column
+// Sketch panel width: one 16-lane group per panel column, 32 columns (512
+// threads), or 16 (256 threads, 512 registers per lane) when the sample
+// column takes 64 or more registers per lane.
+template <int RPT>
+constexpr int panel_width() { return RPT >= 64 ? 16 : 32; }
 constexpr int kTrailThreads = 256;             // 16 trailing columns per workgroup
 constexpr int kBigTri = kWH * (kWH + 1) / 2;   // packed 64-triangle
 
 struct BigSketchArgs {
   int32_t n, s;
   int32_t c0;      // first column of the panel
+  int32_t pw;      // panel width (panel_width<RPT>())
   double* As;      // s x n, ld s: sample; column k holds reflector v_k once formed
   double* tau;     // [n]
   double* Rg;      // n x n row-major: R of the sample as formed (before sign normalization)
@@ -64,7 +68,8 @@ __device__ __forceinline__ double slot_value(const double (&W)[RPT], int t) {
 __device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
 
 template <int RPT>
-__global__ __launch_bounds__(kPanelThreads) void k_sketch_panel(BigSketchArgs a) {
+__global__ __launch_bounds__(16 * panel_width<RPT>()) void k_sketch_panel(BigSketchArgs a) {
+  constexpr int PW = panel_width<RPT>(), NT = 16 * PW;
   __shared__ double vbuf[2][16 * RPT];
   __shared__ double tau_s[2];
   // bad[k & 1] = k when reflector k has a zero or non-finite norm (written in
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_sketch_panel(BigSketchArgs a)
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int l16 = lane & 15, q = lane >> 4;
   const int j = c0 + 4 * wave + q;  // my column
-  const int kend = min(c0 + kPanelW, n);
+  const int kend = min(c0 + PW, n);
   double W[RPT];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_sketch_panel(BigSketchArgs a)
     if (bad[k & 1] >= 0) break;
     // Reflector k (in LDS since the last barrier) replaces sample column k,
     // where the trailing-column kernel reads it: one value per thread.
-    for (int r = threadIdx.x; r < s; r += kPanelThreads) a.As[r + (int64_t)k * s] = vbuf[k & 1][r];
+    for (int r = threadIdx.x; r < s; r += NT) a.As[r + (int64_t)k * s] = vbuf[k & 1][r];
     if (j > k && j < kend) apply(k);
     if (k + 1 < kend && wave == ((k + 1 - c0) >> 2)) reflector(k + 1);
     __syncthreads();
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(kTrailThreads) void k_sketch_trail(BigSketchArgs a)
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int l16 = lane & 15, q = lane >> 4;
   const int n = a.n, s = a.s, c0 = a.c0;
-  const int kend = min(c0 + kPanelW, n);
+  const int kend = min(c0 + a.pw, n);
   const int j = kend + 16 * (int)blockIdx.x + 4 * wave + q;
   double W[RPT];
 #pragma unroll
@@ -268,18 +273,46 @@ struct BigTrsmArgs {
   const int32_t* info;
 };
 
+// The update loop keeps the B operands of the next kDepth k-chunks (over the
+// block boundary) in flight while a chunk is multiplied; two waves per SIMD
+// (the register budget of that) hide the rest of the latency.
+constexpr int kDepth = 2;
+
 __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
+  constexpr int RPT = kWH * kWH / kPassThreads;  // U block values per thread
   __shared__ double rq[2][kWH * kR12Ld];  // U(64Q .., 64P ..) blocks, double buffered
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int P = a.P, c0 = kWH * P;
   const int ncols = min(kWH, a.n - c0);
+  const int nit = 16 * P;  // k-chunks of the update
   const int64_t panels = (a.m + kWave - 1) / kWave;
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+  // U(64 Qb .., 64 P ..) into LDS buffer buf
+  auto load_u = [&](int Qb, int buf) __attribute__((always_inline)) {
+    const double* src = a.full + (int64_t)(kWH * Qb) * a.nmax + c0;
+#pragma unroll 4
+    for (int u = 0; u < RPT; ++u) {
+      const int e = threadIdx.x + u * kPassThreads;
+      rq[buf][(e / kWH) * kR12Ld + e % kWH] = src[(int64_t)(e / kWH) * a.nmax + e % kWH];
+    }
+  };
   for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
     const int64_t r0 = (pg * kPassWaves + wave) * kWave;
     const bool valid = r0 + lane < a.m;
+    // -A1(rows, k-chunk it) for the four row blocks
+    auto fetch_b = [&](int it, double (&dst)[4]) __attribute__((always_inline)) {
+      const int col = 4 * it + g;  // < 64 P <= n - 1 when it < nit
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int64_t row = r0 + 16 * rb + i16;
+        dst[rb] = (it < nit && row < a.m) ? -a.W[row + (int64_t)col * a.ldw] : 0.0;
+      }
+    };
+    double ring[kDepth][4];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) fetch_b(d, ring[d]);
     d4 acc[4][4];
     {
       int nc = ncols;
@@ -299,28 +332,27 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
       }
     }
     __syncthreads();  // the previous panel group's readers of rq are done
+    if (P > 0) load_u(0, 0);
+    __syncthreads();
     for (int Qb = 0; Qb < P; ++Qb) {
       const int buf = Qb & 1;
-      const double* src = a.full + (int64_t)(kWH * Qb) * a.nmax + c0;
-      for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads)
-        rq[buf][(e / kWH) * kR12Ld + e % kWH] = src[(int64_t)(e / kWH) * a.nmax + e % kWH];
-      __syncthreads();
-      const double* X = a.W + (int64_t)(kWH * Qb) * a.ldw;
-#pragma unroll 2
+      // buffer buf ^ 1 was last read in block Qb - 1, before the last barrier
+      if (Qb + 1 < P) load_u(Qb + 1, buf ^ 1);
+      const double* uq = &rq[buf][g * kR12Ld + i16];
+#pragma unroll
       for (int kc = 0; kc < 16; ++kc) {
         double b[4];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          const int64_t row = r0 + 16 * rb + i16;
-          b[rb] = (row < a.m) ? -X[row + (int64_t)(4 * kc + g) * a.ldw] : 0.0;
-        }
+        for (int rb = 0; rb < 4; ++rb) b[rb] = ring[kc % kDepth][rb];
+        fetch_b(16 * Qb + kc + kDepth, ring[kc % kDepth]);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          const double u = rq[buf][(4 * kc + g) * kR12Ld + 16 * cb + i16];
+          const double u = uq[4 * kc * kR12Ld + 16 * cb];
 #pragma unroll
           for (int rb = 0; rb < 4; ++rb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][cb], 0, 0, 0);
         }
       }
+      __syncthreads();
     }
     double vals[4][16];
 #pragma unroll
@@ -470,22 +502,61 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 }
 
 // Line 6: Q = A1 R2^{-1} with the explicit inverse T2 (nmax x nmax row-major,
-// zero outside the n x n upper triangle), in place over A1.  A workgroup takes
-// kBRows 16-row blocks at a time; wave w owns the 16-column blocks w, w + 4,
-// ... (balanced over the triangle).  All four waves read every column of the
-// rows, so the results are stored only after a barrier.  MFMA layout as in
+// zero outside the n x n upper triangle), in place over A1.  One workgroup per
+// CU takes 64 rows at a time; wave w owns the 16-column
+// blocks w, w + 4, ... (balanced over the triangle) for all four row blocks,
+// with the accumulators in AGPRs.  The contraction runs in stages of 16 rows
+// of T2 (four 4-wide k-chunks; 8 rows for nmax >= 384, so that a stage in
+// flight fits the registers): while a stage is multiplied from LDS, the next
+// stage of T2 and the next 16 columns of the rows' A1 are already being loaded
+// into registers; each stage is stored to the other LDS buffer after the
+// multiply, then one barrier.  All waves read every column of the rows, so
+// the results are stored only after a final barrier.  MFMA layout as in
 // k_passB: A operand T2(4 kc + l/16, 16 cb + l%16), B operand A1(row l%16,
 // 4 kc + l/16), result Q(row l%16, 16 cb + 4 v + l/16) in register v.
-constexpr int kBRows = 2;
+// 16-row blocks per workgroup iteration (64 rows; one workgroup per CU, the
+// accumulators in AGPRs).
+template <int NMAX>
+constexpr int passb_rows() { return 4; }
 
 template <int NMAX>
-__global__ __launch_bounds__(kPassThreads) void k_passB_big(PassBArgs a) {
+__global__ __launch_bounds__(kPassThreads, 1) void k_passB_big(PassBArgs a) {
+  constexpr int kBRows = passb_rows<NMAX>();
   constexpr int NB = NMAX / 16, PERW = NB / kPassWaves;
+  constexpr int SK = NMAX >= 384 ? 2 : 4;              // 4-wide k-chunks per stage (registers)
+  constexpr int SR = 4 * SK;                           // T2 rows per stage
+  constexpr int TLD = NMAX + 4;                        // LDS row stride of a T2 stage
+  constexpr int TPT = SR * NMAX / kPassThreads;        // T2 stage values per thread
+  __shared__ double ts[2][SR * TLD];
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int nkc = (a.n + 3) / 4;
+  const int n = a.n;
+  const int nstage = (n + SR - 1) / SR;
   const int64_t groups = (a.m + 16 * kBRows - 1) / (16 * kBRows);
+  double tv[TPT];               // next T2 stage
+  double bv[SK][kBRows];        // next stage of A1: SK k-chunks x row blocks
+  auto fetch = [&](int64_t rbase, int st) __attribute__((always_inline)) {
+    const double* t2 = a.T2 + (int64_t)SR * st * NMAX + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) tv[u] = (st < nstage) ? t2[u * kPassThreads] : 0.0;
+#pragma unroll
+    for (int kk = 0; kk < SK; ++kk) {
+      const int col = SR * st + 4 * kk + g4;
+#pragma unroll
+      for (int rb = 0; rb < kBRows; ++rb) {
+        const int64_t row = rbase + 16 * rb + i16;
+        bv[kk][rb] = (st < nstage && row < a.m && col < n) ? a.Q[row + (int64_t)col * a.ldq] : 0.0;
+      }
+    }
+  };
+  auto put = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int e = threadIdx.x + u * kPassThreads;
+      ts[buf][(e / NMAX) * TLD + e % NMAX] = tv[u];
+    }
+  };
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     const int64_t rbase = grp * 16 * kBRows;
     d4 acc[kBRows][PERW];
@@ -493,27 +564,37 @@ __global__ __launch_bounds__(kPassThreads) void k_passB_big(PassBArgs a) {
     for (int rb = 0; rb < kBRows; ++rb)
 #pragma unroll
       for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kc = 0; kc < nkc; ++kc) {
-      const int col = 4 * kc + g4;
-      double b[kBRows];
+    fetch(rbase, 0);
+    __syncthreads();  // the previous iteration's readers of ts are done
+    put(0);
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+      const int buf = st & 1;
+      double b[SK][kBRows];
 #pragma unroll
-      for (int rb = 0; rb < kBRows; ++rb) {
-        const int64_t row = rbase + 16 * rb + i16;
-        b[rb] = (row < a.m && col < a.n) ? a.Q[row + (int64_t)col * a.ldq] : 0.0;
-      }
-      const double* trow = a.T2 + (int64_t)col * NMAX + i16;
+      for (int kk = 0; kk < SK; ++kk)
 #pragma unroll
-      for (int i = 0; i < PERW; ++i) {
-        const int cb = wave + kPassWaves * i;
-        if (cb >= (kc >> 2)) {
-          const double u = trow[16 * cb];
+        for (int rb = 0; rb < kBRows; ++rb) b[kk][rb] = bv[kk][rb];
+      fetch(rbase, st + 1);
+      const double* tr = &ts[buf][g4 * TLD + i16];
 #pragma unroll
-          for (int rb = 0; rb < kBRows; ++rb)
-            acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][i], 0, 0, 0);
+      for (int kk = 0; kk < SK; ++kk) {
+        const int kc = SK * st + kk;
+#pragma unroll
+        for (int i = 0; i < PERW; ++i) {
+          const int cb = wave + kPassWaves * i;
+          if (cb >= (kc >> 2)) {  // T2 is zero left of its diagonal
+            const double u = tr[4 * kk * TLD + 16 * cb];
+#pragma unroll
+            for (int rb = 0; rb < kBRows; ++rb)
+              acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[kk][rb], acc[rb][i], 0, 0, 0);
+          }
         }
       }
+      if (st + 1 < nstage) put(buf ^ 1);
+      __syncthreads();
     }
-    __syncthreads();  // every wave has read these rows of A1
+    // every wave has read these rows of A1 (the last barrier above)
 #pragma unroll
     for (int rb = 0; rb < kBRows; ++rb) {
       const int64_t row = rbase + 16 * rb + i16;
@@ -523,7 +604,7 @@ __global__ __launch_bounds__(kPassThreads) void k_passB_big(PassBArgs a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int col = 16 * (wave + kPassWaves * i) + 4 * v + g4;
-            if (col < a.n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
+            if (col < n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
           }
       }
     }

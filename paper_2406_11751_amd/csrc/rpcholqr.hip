@@ -357,10 +357,12 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     ba.info = inf;
     with_big_rpt(p.rpt, [&](auto rp) {
       constexpr int RPT = decltype(rp)::value;
-      for (int c0 = 0; c0 < n; c0 += kPanelW) {
+      constexpr int PW = panel_width<RPT>();
+      ba.pw = PW;
+      for (int c0 = 0; c0 < n; c0 += PW) {
         ba.c0 = c0;
-        hipLaunchKernelGGL((k_sketch_panel<RPT>), dim3(1), dim3(kPanelThreads), 0, st, ba);
-        const int64_t trail = n - std::min<int64_t>(c0 + kPanelW, n);
+        hipLaunchKernelGGL((k_sketch_panel<RPT>), dim3(1), dim3(16 * PW), 0, st, ba);
+        const int64_t trail = n - std::min<int64_t>(c0 + PW, n);
         if (trail > 0)
           hipLaunchKernelGGL((k_sketch_trail<RPT>), dim3((unsigned)((trail + 15) / 16)), dim3(kTrailThreads), 0, st,
                              ba);
@@ -460,10 +462,11 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     pb.Q = Q;
     pb.ldq = ldq;
     pb.info = inf;
-    const int64_t groups = (m + 16 * kBRows - 1) / (16 * kBRows);
-    const unsigned grid = (unsigned)std::min<int64_t>(groups, 4 * cus);
     with_big_nmax(p.nmax, [&](auto nm) {
-      hipLaunchKernelGGL((k_passB_big<decltype(nm)::value>), dim3(grid), dim3(kPassThreads), 0, st, pb);
+      constexpr int NM = decltype(nm)::value, rows = 16 * passb_rows<NM>();
+      const int64_t groups = (m + rows - 1) / rows;
+      const unsigned grid = (unsigned)std::min<int64_t>(groups, cus);
+      hipLaunchKernelGGL((k_passB_big<NM>), dim3(grid), dim3(kPassThreads), 0, st, pb);
     });
   }
   if (!launched()) return RPCHOLQR_EHIP;

@@ -69,6 +69,35 @@ def gen_usv(m: int, n: int, kappa: float, seed: int, backend: str = "numpy", dev
     raise ValueError(f"unknown backend {backend!r}")
 
 
+def gen_usv_polar(m: int, n: int, kappa: float, seed: int, device=None, chunk_rows: int = 1 << 20):
+    """A = U diag(sigma) V^T as gen_usv, for device-resident inputs too large for
+    a QR of the Gaussian matrix next to A (the 16,000,000 x 512 workload is
+    65.5 GB).  U is the orthonormal polar factor X (X^T X)^{-1/2} of the m x n
+    standard Gaussian X, which is Haar-distributed like the Q factor of X (it
+    differs from it by an n x n orthogonal factor that is independent of it);
+    V is the Q factor of an n x n Gaussian matrix, sign-fixed.  A = X M with
+    M = (X^T X)^{-1/2} diag(sigma) V^T is formed in place of X, chunk_rows rows
+    at a time, so the input costs one m x n buffer.  Column-major (strides
+    (1, m)); torch generator seeded with `seed`."""
+    import torch
+
+    dev = torch.device(device or "cuda")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    X = torch.randn((n, m), generator=g, device=dev, dtype=torch.float64).t()
+    evals, evecs = torch.linalg.eigh(X.t() @ X)
+    W = (evecs * evals.rsqrt()[None, :]) @ evecs.t()
+    Y = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64).t()
+    V, RV = torch.linalg.qr(Y)
+    V = V * torch.sign(torch.diagonal(RV))[None, :]
+    sig = torch.as_tensor(sigma_profile(n, kappa), device=dev, dtype=torch.float64)
+    M = (W * sig[None, :]) @ V.t()
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        X[r0:r1] = X[r0:r1] @ M
+    return X
+
+
 def checksum(A: np.ndarray) -> str:
     """SHA-256 of the column-major bytes of A."""
     return hashlib.sha256(np.asfortranarray(A, dtype=np.float64).tobytes(order="F")).hexdigest()

@@ -35,9 +35,16 @@ def _tall_norm2(M) -> float:
     return float(np.sqrt(max(_sym_norm2(S), 0.0)))
 
 
-def residual(A, Q, R) -> float:
+def residual(A, Q, R, chunk_rows: int = 1 << 20) -> float:
     if _is_torch(A):
-        return _tall_norm2(A - Q @ R) / _tall_norm2(A)
+        # (A - QR)^T (A - QR) summed over row chunks: no m x n temporary
+        S = None
+        for r0 in range(0, A.shape[0], chunk_rows):
+            D = A[r0:r0 + chunk_rows] - Q[r0:r0 + chunk_rows] @ R
+            P = D.t() @ D
+            S = P if S is None else S + P
+        res2 = max(_sym_norm2(S.cpu().numpy()), 0.0)
+        return float(np.sqrt(res2)) / _tall_norm2(A)
     A = np.asarray(A, dtype=np.float64)
     return _tall_norm2(A - Q @ R) / _tall_norm2(A)
 
