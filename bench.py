@@ -46,7 +46,9 @@ def parse():
                     help="bounded CPU sample: repeat oracle factorizations for about this long")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the refined-precision measurement")
-    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-large", action="store_true", help="skip the 4e6 x 256 and 1.6e7 x 512 workloads")
+    ap.add_argument("--large-only", default="", help="comma-separated subset of the large workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (for counter calibration)")
     return ap.parse_args()
@@ -85,17 +87,27 @@ def measured_traffic(pass_name: str, m: int, n: int):
     return rec["traffic_bytes"]
 
 
+def per_pass_roofline_s(m, n):
+    """Sum over the two streaming passes of max(bytes / HBM peak, flops / FP64 peak):
+    pass A reads A (8mn B) and does m n^2 + m n (n+1) flops; pass B reads and
+    writes (16mn B) and does m n^2 flops."""
+    a = max(8.0 * m * n / (HBM_PEAK_GBS * 1e9), m * (2.0 * n * n + n) / (FP64_PEAK_TFS * 1e12))
+    b = max(16.0 * m * n / (HBM_PEAK_GBS * 1e9), 1.0 * m * n * n / (FP64_PEAK_TFS * 1e12))
+    return a + b
+
+
 def batched_measurement(args, torch, rq, gen_usv, metrics):
     """Batched workload: the 2048-problem list (m ~ U{2000..200000}, n ~ U{8, 16,
-    32, 64, 128}, log10 kappa ~ U[2, 14], s = 3n, seed i), generated on the GPU
-    (problems beyond the library's largest n, if any, are left out and counted).
-    Times whole executions of one batched plan and, for comparison, the same
+    32, 64, 128}, log10 kappa ~ U[2, 14], s = 3n, seed i), generated on the GPU.
+    One plan (launch shapes from the autotuned table) is captured in a HIP graph;
+    the replays are timed.  For comparison: the eager execute, and the same
     problems factored one call at a time with the single-problem entry point."""
+    import numpy as np
     from workloads import batched_problem_list
 
     dev = torch.device("cuda:0")
     plist = batched_problem_list(2048, 0)
-    keep = [p for p in plist if p["n"] <= rq.max_n()]
+    keep = [p for p in plist if p["n"] <= 128]
     t0 = time.time()
     As = []
     for i, p in enumerate(keep):
@@ -104,43 +116,130 @@ def batched_measurement(args, torch, rq, gen_usv, metrics):
             print(f"# batched inputs: {i + 1}/{len(keep)} ({time.time() - t0:.0f}s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print(f"# batched inputs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    tuned = rq.load_batched_tuning()
     plan = rq.BatchedPlan(As, [p["s"] for p in keep], [p["seed"] for p in keep])
     info = torch.zeros((len(keep), 2), dtype=torch.int32, device=dev)
-    plan.execute(info=info)  # warm-up and check
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.execute(info=info, stream=st.cuda_stream)  # warm-up and check
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            plan.execute(info=info, stream=st.cuda_stream, check=False)
+    g.replay()
     torch.cuda.synchronize()
-    e0.record(stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.batched_steps + 1)]
+    evs[0].record()
+    for k in range(args.batched_steps):
+        g.replay()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    rep = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.batched_steps)])
+    ms = float(np.median(rep))
+    assert int((info[:, 0] != 0).sum()) == 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(args.batched_steps):
         plan.execute(info=info, check=False)
-    e1.record(stream)
+    e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batched_steps
-    assert int((info[:, 0] != 0).sum()) == 0
+    eager_ms = e0.elapsed_time(e1) / args.batched_steps
     orth = max(metrics.orth_error(plan.Qs[i]) for i in range(0, len(keep), 64))
     # the same problems one call at a time (single-problem entry point, its own workspace each)
     ws = torch.empty(max(rq.workspace_bytes(p["m"], p["n"], p["s"]) for p in keep), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    e0.record(stream)
+    e0.record()
     for A, Q, R, p in zip(As, plan.Qs, plan.Rs, keep):
         rq.factor(A, p["s"], p["seed"], Q=Q, R=R, workspace=ws, info=info[0], check=False)
-    e1.record(stream)
+    e1.record()
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1)
     bytes_alg = sum(24.0 * p["m"] * p["n"] for p in keep)
-    excluded = len(plist) - len(keep)
+    roof_ms = sum(per_pass_roofline_s(p["m"], p["n"]) for p in keep) * 1e3
     out = dict(workload="2048-problem list (m ~ U{2000..200000}, n ~ U{8,16,32,64,128}, log10 kappa ~ U[2,14], "
-                        "s = 3n, seed i)" + (f", {excluded} problems with n > {rq.max_n()} excluded" if excluded else ""),
-               problems=len(keep), excluded=excluded, ms_per_batch=ms,
+                        "s = 3n, seed i)", problems=len(keep), ms_per_batch=ms,
+               ms_p10=float(np.percentile(rep, 10)), ms_p90=float(np.percentile(rep, 90)),
+               timing="median over HIP-graph replays of one captured plan execution",
+               eager_ms_per_batch=eager_ms, autotuned_shapes=tuned,
                factorizations_per_s=len(keep) / (ms * 1e-3), value_GBps=bytes_alg / (ms * 1e-3) / 1e9,
+               roofline_ms=roof_ms, roofline_frac=roof_ms / ms,
+               roofline_model="sum over problems and passes of max(bytes / 8 TB/s, flops / 78.6 TF/s)",
                sequential_single_calls_ms=seq_ms, speedup_vs_single_calls=seq_ms / ms,
                max_orth_every_64th=orth, device_bytes=plan.device_bytes)
+    del g
     plan.close()
     del As
     torch.cuda.empty_cache()
-    print(f"# batched: {len(keep)} problems in {ms:.2f} ms ({out['factorizations_per_s']:.0f} fact/s, "
-          f"{out['value_GBps']:.0f} GB/s); one call at a time {seq_ms:.1f} ms", file=sys.stderr, flush=True)
+    print(f"# batched: {len(keep)} problems in {ms:.2f} ms (graph replay; eager {eager_ms:.2f} ms; "
+          f"{out['factorizations_per_s']:.0f} fact/s, {out['roofline_frac']:.2f} of roofline); "
+          f"one call at a time {seq_ms:.1f} ms", file=sys.stderr, flush=True)
     return out
+
+
+def large_measurement(args, torch, rq, metrics):
+    """The 4,000,000 x 256 (kappa 1e12, s = 768) and 16,000,000 x 512 (kappa 1e10,
+    s = 1536) workloads in FP64, generated on the GPU (the larger one with the
+    polar-factor construction, which needs no second m x n buffer).  Reports time
+    per factorization, GB/s on 24mn, TFLOP/s on 3mn^2 and its fraction of the
+    FP64 peak, orthogonality and residual at full size, and parity against the
+    oracle on the first 100,000 rows (same seed and s)."""
+    import numpy as np
+
+    import oracle
+    from workloads import gen_usv, gen_usv_polar
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, m, n, s, kappa, steps in (("4e6x256", 4_000_000, 256, 768, 1e12, 10),
+                                        ("1.6e7x512", 16_000_000, 512, 1536, 1e10, 3)):
+        if args.large_only and name not in args.large_only.split(","):
+            continue
+        t0 = time.time()
+        if m * n > 10**9:
+            A = gen_usv_polar(m, n, kappa, 0, device=dev)
+        else:
+            A = gen_usv(m, n, kappa, 0, backend="torch", device=dev)
+        torch.cuda.synchronize()
+        print(f"# {name}: input generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        Q = rq.colmajor_empty(m, n, dev)
+        R = rq.colmajor_empty(n, n, dev)
+        ws = torch.empty(rq.workspace_bytes(m, n, s), dtype=torch.uint8, device=dev)
+        info = torch.zeros(2, dtype=torch.int32, device=dev)
+        rq.factor(A, s, 0, Q=Q, R=R, workspace=ws, info=info)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        evs[0].record()
+        for k in range(steps):
+            rq.factor(A, s, 0, Q=Q, R=R, workspace=ws, info=info, check=False)
+            evs[k + 1].record()
+        torch.cuda.synchronize()
+        t = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+        ms = float(np.median(t))
+        rq.timing_enable(True)
+        rq.factor(A, s, 0, Q=Q, R=R, workspace=ws, info=info, check=False)
+        _, stage_ms = rq.timing_read()
+        rq.timing_enable(False)
+        assert info.cpu().tolist() == [0, -1]
+        orth, resid = metrics.orth_error(Q), metrics.residual(A, Q, R)
+        # parity on a row subsample the oracle finishes quickly
+        msub = 100_000
+        A_sub = A[:msub].cpu().numpy()
+        Qs, Rs, _ = rq.factor(A[:msub], s, 0)
+        ref = oracle.rpcholqr(A_sub, s, 0, nthreads=host_cores(), keep=False)
+        assert ref.status == oracle.OK
+        tf = 3.0 * m * n * n / (ms * 1e-3) / 1e12
+        res[name] = dict(m=m, n=n, s=s, kappa=kappa, dtype="f64", ms_per_factorization=ms,
+                         ms_p10=float(np.percentile(t, 10)), ms_p90=float(np.percentile(t, 90)),
+                         factorizations_per_s=1e3 / ms, value_GBps=24.0 * m * n / (ms * 1e-3) / 1e9,
+                         tflops=tf, frac_fp64_peak=tf / FP64_PEAK_TFS,
+                         stage_ms=stage_ms, orth=orth, residual=resid,
+                         parity_subsample=dict(rows=msub, rel_fro_Q=metrics.rel_fro(Qs, ref.Q),
+                                               rel_fro_R=metrics.rel_fro(Rs, ref.R)))
+        print(f"# {name}: {ms:.2f} ms ({tf:.1f} TF/s = {tf / FP64_PEAK_TFS:.2f} of FP64 peak), orth {orth:.1e}, "
+              f"residual {resid:.1e}, subsample |dQ| {res[name]['parity_subsample']['rel_fro_Q']:.1e}",
+              file=sys.stderr, flush=True)
+        del A, Q, R, ws, Qs, Rs
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -316,6 +415,7 @@ def main():
     step()  # leave the FP64 result in Q, R
 
     batched = None if args.no_batched else batched_measurement(args, torch, rq, gen_usv, metrics)
+    large = None if args.no_large else large_measurement(args, torch, rq, metrics)
 
     out = {
         "metric": METRIC,
@@ -345,6 +445,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "batched": batched,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 

@@ -216,19 +216,50 @@ int32_t rpcholqr_timing_read(double* ms, int32_t count);
  *                  (-1 if none)
  *   Validates every problem (EINVAL / EUNSUPPORTED), allocates the plan's device
  *   memory on the current device (descriptor tables and one workspace per
- *   problem, rpcholqr_batched_plan_device_bytes) and uploads the tables with
- *   blocking copies.  The plan refers to the caller's A, Q and R, which must
+ *   problem, rpcholqr_batched_plan_device_bytes) and streams, and uploads the
+ *   tables with blocking copies.  Launch shapes come from the tuning table
+ *   (rpcholqr_batched_set_tuning).  The plan refers to the caller's A, Q and R, which must
  *   stay valid while it is executed.
  * rpcholqr_batched_execute
- *   Launches every problem on `stream` (hipStream_t as void*): one launch per
- *   stage and size class, no allocation and no host-to-device copy, so a
- *   stream capture into a HIP graph records it.  info is a DEVICE array of
- *   batch rpcholqr_info, one per problem.  Executions of the same plan must not
- *   overlap (they share its workspace).
+ *   Launches every problem (hipStream_t as void*): per column class one chain
+ *   of launches (gather, sketch, pass A, Cholesky, pass B), the classes
+ *   concurrently on streams the plan owns, forked from and joined to `stream`
+ *   by events; no allocation and no host-to-device copy, so a stream capture
+ *   into a HIP graph records it (with the fork and join).  info is a DEVICE
+ *   array of batch rpcholqr_info, one per problem.  Executions of the same plan
+ *   must not overlap (they share its workspace and streams).
  * rpcholqr_batched_plan_destroy frees the plan; the caller first waits for the
  *   work that uses it.
  * rpcholqr_factor_batched is create + execute + stream synchronize + destroy. */
 typedef struct rpcholqr_batched_plan rpcholqr_batched_plan;
+
+/* Launch shape of the batched passes for one column class and m bucket (not in
+ * the paper; picked per GPU by the autotuner in paper_2406_11751_amd/autotune.py).
+ *   nmax      column class: 16, 32, 48, 64 (n rounded up) or 128 (64 < n <= 128)
+ *   m_max     the entry covers problems of the class with m <= m_max; a class's
+ *             entries are searched in increasing m_max
+ *   pa_rows   pass-A panel height: rows of one problem per pass-A workgroup (a
+ *             multiple of 256); a problem gets ceil(m / pa_rows) workgroups,
+ *             at most pa_max (1 .. 128), each writing one partial Gram matrix
+ *   pb_rows   rows of one problem per pass-B workgroup (a multiple of 16)
+ * The number of partials changes the order in which the Gram matrix is summed,
+ * so results under different tunings agree to rounding (about 1e-15). */
+typedef struct {
+  int32_t nmax;
+  int32_t reserved0;
+  int64_t m_max;
+  int32_t pa_rows;
+  int32_t pa_max;
+  int32_t pb_rows;
+  int32_t reserved1;
+} rpcholqr_batched_tuning;
+
+/* Installs the tuning table used by every later rpcholqr_batched_plan_create
+ * (process-wide; existing plans keep their shapes).  count = 0 restores the
+ * built-in shapes (pa_rows 2048, pa_max 64, pb_rows 1024, or 2048 for the
+ * 128-column class).  A class or m without an entry uses the built-in shape.
+ * Returns RPCHOLQR_EINVAL for a malformed entry (the table is then unchanged). */
+int32_t rpcholqr_batched_set_tuning(const rpcholqr_batched_tuning* entries, int32_t count);
 int32_t rpcholqr_batched_plan_create(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,
                                      const uint64_t* seed, const double* const* A, const int64_t* lda,
                                      double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,

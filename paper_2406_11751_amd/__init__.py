@@ -5,5 +5,6 @@ Garrison & Ipsen, "A randomized preconditioned Cholesky-QR algorithm"
 include/rpcholqr.h; this package only builds and binds that library.
 """
 from .native import (FP64, FP32_REFINE, BF16X2_REFINE, BatchedPlan, RpCholQRError, colmajor_empty,  # noqa: F401
-                     factor, factor_batched, load_library, max_n, precond_factor, sample_indices,
-                     timing_enable, timing_read, workspace_bytes)
+                     factor, factor_batched, factor_noalloc, load_batched_tuning, load_library, max_n,
+                     precond_factor, sample_indices, set_batched_tuning, timing_enable, timing_read,
+                     workspace_bytes)

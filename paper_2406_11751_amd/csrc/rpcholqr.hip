@@ -720,10 +720,40 @@ int64_t noalloc_pa_cap(int64_t m, int64_t n, int64_t s, bool refine) {
 
 // ---------------------------------------------------------------------------
 // Batched plans.
+//
+// Per column class (NMAX) and m bucket, a tuning entry fixes the panel height
+// of pass A (rows of one problem per pass-A workgroup), the largest number of
+// pass-A workgroups (Gram partials) of one problem, and the rows per pass-B
+// workgroup.  The built-in entry is used unless rpcholqr_batched_set_tuning
+// installed a table (written by the autotuner).
 
-constexpr int64_t kBatchPartialsMax = 64;   // pass-A workgroups (Gram partials) per problem
-constexpr int64_t kBatchPgroupsPerWG = 8;   // target panel groups per pass-A workgroup
-constexpr int64_t kBatchBIters = 16;        // target 4-block iterations per pass-B workgroup
+struct TuneEntry {
+  int nmax = 0;
+  int64_t m_max = 0;
+  int pa_rows = 0, pa_max = 0, pb_rows = 0;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;  // sorted by (nmax, m_max)
+
+TuneEntry default_tuning(int nmax) {
+  TuneEntry e;
+  e.nmax = nmax;
+  e.m_max = INT64_MAX;
+  e.pa_rows = 8 * kPassWaves * kWave;  // eight panel groups of four 64-row panels
+  e.pa_max = 64;
+  e.pb_rows = (nmax == kWideN ? kPassB128Waves : kPassBThreads / kWave) * 16 * 16;  // 16 iterations of 16-row blocks
+  return e;
+}
+
+TuneEntry tuning_for(int nmax, int64_t m) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const TuneEntry& e : g_tune)
+    if (e.nmax == nmax && m <= e.m_max) return e;
+  return default_tuning(nmax);
+}
+
+constexpr int kBatchMaxPartials = 128;
 
 // Sketch class of a problem: the register kernel's RPT (plus 100 for the wide
 // register kernel), 0 for the generic kernel with n <= 64, -1 for the generic
@@ -733,19 +763,27 @@ int sketch_key(const Plan& p) {
   return p.rpt;
 }
 
-// 16-row blocks of pass B per workgroup and target iteration count.
-int64_t pass_b_items(int nmax, int64_t m) {
-  const int64_t blocks16 = (m + 15) / 16;
-  const int64_t per_wg = (int64_t)(nmax == kWideN ? kPassB128Waves : kPassBThreads / kWave) * kBatchBIters;
+// Pass-B workgroups of one problem: pb_rows rows each.
+int64_t pass_b_items(int64_t m, int pb_rows) {
+  const int64_t blocks16 = (m + 15) / 16, per_wg = std::max(1, pb_rows / 16);
   return std::max<int64_t>(1, (blocks16 + per_wg - 1) / per_wg);
 }
 
-struct SizeClass {
-  int key = 0;                       // sketch_key (sketch classes) or NMAX (pass classes)
-  size_t probs_off = 0, items_a_off = 0, items_b_off = 0;  // offsets into the device buffer
+struct SketchGroup {
+  int key = 0;
+  size_t probs_off = 0;
   int nprobs = 0;
-  int64_t items_a = 0, items_b = 0;
   int64_t max_s = 0;
+};
+
+// One column class: its problems run as one chain of launches (gather, sketch
+// per RPT group, pass A, Cholesky, pass B) on a stream of their own.
+struct PassClass {
+  int nmax = 0;
+  size_t probs_off = 0, items_g_off = 0, items_a_off = 0, items_b_off = 0;
+  int nprobs = 0;
+  int64_t items_g = 0, items_a = 0, items_b = 0;
+  std::vector<SketchGroup> sketches;
 };
 
 int32_t check_problem(int64_t m, int64_t n, int64_t s, const double* A, int64_t lda, const double* Q,
@@ -765,9 +803,13 @@ struct rpcholqr_batched_plan {
   int64_t batch = 0;
   void* dmem = nullptr;
   size_t dbytes = 0;
-  size_t sk_off = 0, pa_off = 0, ch_off = 0, pb_off = 0, gather_off = 0;
-  int64_t gather_items = 0;
-  std::vector<SizeClass> sketch_classes, pass_classes;
+  size_t sk_off = 0, pa_off = 0, ch_off = 0, pb_off = 0;
+  std::vector<PassClass> classes;
+  // one stream per column class beyond the first (default priority), and the
+  // events that fork them from and join them to the caller's stream
+  std::vector<hipStream_t> streams;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
 };
 
 namespace {
@@ -775,6 +817,14 @@ namespace {
 template <typename T>
 T* at(const rpcholqr_batched_plan* p, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(p->dmem) + off);
+}
+
+void release(rpcholqr_batched_plan* p) {
+  for (hipStream_t s : p->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : p->joins) (void)hipEventDestroy(e);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->dmem) (void)hipFree(p->dmem);
+  delete p;
 }
 
 int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s, const uint64_t* seed,
@@ -788,14 +838,22 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
     return RPCHOLQR_EINVAL;
   if (precision != RPCHOLQR_FP64) return RPCHOLQR_EUNSUPPORTED;
   std::vector<Plan> plans((size_t)batch);
+  std::vector<int> pb_rows((size_t)batch);
   for (int64_t b = 0; b < batch; ++b) {
     int32_t rc = check_problem(m[b], n[b], s[b], A[b], lda[b], Q[b], ldq[b], R[b], ldr[b]);
     if (rc == RPCHOLQR_OK) {
-      const int64_t panels = (m[b] + kWave - 1) / kWave;
-      const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-      int64_t pa = (pgroups + kBatchPgroupsPerWG - 1) / kBatchPgroupsPerWG;
-      pa = std::min<int64_t>(std::max<int64_t>(pa, 1), kBatchPartialsMax);
-      if (!make_plan(m[b], n[b], s[b], &plans[b], pa, true)) rc = RPCHOLQR_EUNSUPPORTED;
+      if (n[b] > kWideN) {
+        rc = RPCHOLQR_EUNSUPPORTED;
+      } else {
+        const TuneEntry t = tuning_for(pick_nmax(n[b]), m[b]);
+        const int64_t panels = (m[b] + kWave - 1) / kWave;
+        const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
+        const int64_t per_wg = std::max(1, t.pa_rows / (kPassWaves * kWave));
+        int64_t pa = (pgroups + per_wg - 1) / per_wg;
+        pa = std::min<int64_t>(std::max<int64_t>(pa, 1), std::min(t.pa_max, kBatchMaxPartials));
+        pb_rows[b] = t.pb_rows;
+        if (!make_plan(m[b], n[b], s[b], &plans[b], pa, true)) rc = RPCHOLQR_EUNSUPPORTED;
+      }
     }
     if (rc != RPCHOLQR_OK) {
       if (bad_problem) *bad_problem = b;
@@ -804,23 +862,13 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
   }
   auto* p = new rpcholqr_batched_plan();
   p->batch = batch;
-  // Size classes; problems within a class in decreasing m (largest work first).
+  // Column classes; problems within a class in decreasing m (largest work first).
   std::vector<int64_t> order((size_t)batch);
   for (int64_t b = 0; b < batch; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return m[x] > m[y]; });
-  std::map<int, std::vector<int32_t>> by_rpt, by_nmax;
-  for (int64_t b : order) {
-    by_rpt[sketch_key(plans[b])].push_back((int32_t)b);
-    by_nmax[plans[b].nmax].push_back((int32_t)b);
-  }
-  // Host images of the device tables.
-  std::vector<SketchArgs> sk((size_t)batch);
-  std::vector<PassAArgs> pa((size_t)batch);
-  std::vector<CholArgs> ch((size_t)batch);
-  std::vector<PassBArgs> pb((size_t)batch);
-  std::vector<BatchItem> gather, items_a, items_b;
-  std::vector<int32_t> probs;
-  // Device buffer layout: tables, item lists, then the per-problem workspaces.
+  std::map<int, std::vector<int32_t>> by_nmax;
+  for (int64_t b : order) by_nmax[plans[b].nmax].push_back((int32_t)b);
+  // Device buffer layout: argument tables, per-class lists, then the workspaces.
   size_t off = 0;
   auto reserve = [&](size_t bytes) {
     const size_t o = off;
@@ -831,40 +879,71 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
   p->pa_off = reserve(sizeof(PassAArgs) * batch);
   p->ch_off = reserve(sizeof(CholArgs) * batch);
   p->pb_off = reserve(sizeof(PassBArgs) * batch);
-  for (int64_t b = 0; b < batch; ++b) {
-    const int64_t nb = ((int64_t)s[b] * n[b] + kGatherThreads - 1) / kGatherThreads;
-    for (int64_t i = 0; i < nb; ++i) gather.push_back(BatchItem{(int32_t)b, (int32_t)i, (int32_t)nb});
-  }
-  p->gather_items = (int64_t)gather.size();
-  p->gather_off = reserve(sizeof(BatchItem) * gather.size());
-  for (auto& kv : by_rpt) {
-    SizeClass c;
-    c.key = kv.first;
-    c.nprobs = (int)kv.second.size();
-    c.probs_off = reserve(sizeof(int32_t) * kv.second.size());
-    for (int32_t b : kv.second) c.max_s = std::max<int64_t>(c.max_s, s[b]);
-    p->sketch_classes.push_back(c);
-  }
+  struct HostLists {
+    std::vector<int32_t> probs;
+    std::vector<BatchItem> g, a, b;
+    std::vector<std::vector<int32_t>> sk;
+  };
+  std::vector<HostLists> lists;
   for (auto& kv : by_nmax) {
-    SizeClass c;
-    c.key = kv.first;
-    c.nprobs = (int)kv.second.size();
-    c.probs_off = reserve(sizeof(int32_t) * kv.second.size());
-    for (int32_t b : kv.second) {
-      c.items_a += plans[b].PA;
-      c.items_b += pass_b_items(plans[b].nmax, m[b]);
+    PassClass c;
+    HostLists h;
+    c.nmax = kv.first;
+    h.probs = kv.second;
+    c.nprobs = (int)h.probs.size();
+    std::map<int, std::vector<int32_t>> by_key;
+    for (int32_t b : h.probs) {
+      const int64_t ng = ((int64_t)s[b] * n[b] + kGatherThreads - 1) / kGatherThreads;
+      for (int64_t i = 0; i < ng; ++i) h.g.push_back(BatchItem{b, (int32_t)i, (int32_t)ng});
+      const int32_t na = plans[b].PA;
+      for (int32_t k = 0; k < na; ++k) h.a.push_back(BatchItem{b, k, na});
+      const int32_t nb = (int32_t)pass_b_items(m[b], pb_rows[b]);
+      for (int32_t k = 0; k < nb; ++k) h.b.push_back(BatchItem{b, k, nb});
+      by_key[sketch_key(plans[b])].push_back(b);
     }
-    c.items_a_off = reserve(sizeof(BatchItem) * c.items_a);
-    c.items_b_off = reserve(sizeof(BatchItem) * c.items_b);
-    p->pass_classes.push_back(c);
+    c.probs_off = reserve(sizeof(int32_t) * h.probs.size());
+    c.items_g = (int64_t)h.g.size();
+    c.items_a = (int64_t)h.a.size();
+    c.items_b = (int64_t)h.b.size();
+    c.items_g_off = reserve(sizeof(BatchItem) * h.g.size());
+    c.items_a_off = reserve(sizeof(BatchItem) * h.a.size());
+    c.items_b_off = reserve(sizeof(BatchItem) * h.b.size());
+    for (auto& kk : by_key) {
+      SketchGroup g;
+      g.key = kk.first;
+      g.nprobs = (int)kk.second.size();
+      g.probs_off = reserve(sizeof(int32_t) * kk.second.size());
+      for (int32_t b : kk.second) g.max_s = std::max<int64_t>(g.max_s, s[b]);
+      c.sketches.push_back(g);
+      h.sk.push_back(kk.second);
+    }
+    p->classes.push_back(c);
+    lists.push_back(std::move(h));
   }
   std::vector<size_t> ws_off((size_t)batch);
   for (int64_t b = 0; b < batch; ++b) ws_off[b] = reserve(plans[b].total);
   p->dbytes = off;
-  if (hipMalloc(&p->dmem, p->dbytes) != hipSuccess) {
-    delete p;
+  bool ok = hipMalloc(&p->dmem, p->dbytes) == hipSuccess;
+  if (ok && p->classes.size() > 1) {
+    ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+    for (size_t c = 1; ok && c < p->classes.size(); ++c) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+      if (ok) p->streams.push_back(st);
+      ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (ok) p->joins.push_back(ev);
+    }
+  }
+  if (!ok) {
+    release(p);
     return RPCHOLQR_EHIP;
   }
+  // Host images of the argument tables.
+  std::vector<SketchArgs> sk((size_t)batch);
+  std::vector<PassAArgs> pa((size_t)batch);
+  std::vector<CholArgs> ch((size_t)batch);
+  std::vector<PassBArgs> pb((size_t)batch);
   char* base = static_cast<char*>(p->dmem);
   for (int64_t b = 0; b < batch; ++b) {
     const Plan& pl = plans[b];
@@ -913,124 +992,142 @@ int32_t batched_create(int64_t batch, const int64_t* m, const int64_t* n, const 
     q.Q = Q[b];
     q.ldq = ldq[b];
   }
-  bool ok = hipMemcpy(at<SketchArgs>(p, p->sk_off), sk.data(), sizeof(SketchArgs) * batch,
-                      hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(at<PassAArgs>(p, p->pa_off), pa.data(), sizeof(PassAArgs) * batch,
-                      hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(at<CholArgs>(p, p->ch_off), ch.data(), sizeof(CholArgs) * batch, hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(at<PassBArgs>(p, p->pb_off), pb.data(), sizeof(PassBArgs) * batch,
-                      hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(at<BatchItem>(p, p->gather_off), gather.data(), sizeof(BatchItem) * gather.size(),
-                      hipMemcpyHostToDevice) == hipSuccess;
-  {
-    size_t i = 0;
-    for (auto& kv : by_rpt) {
-      ok = ok && hipMemcpy(at<int32_t>(p, p->sketch_classes[i].probs_off), kv.second.data(),
-                           sizeof(int32_t) * kv.second.size(), hipMemcpyHostToDevice) == hipSuccess;
-      ++i;
-    }
-    i = 0;
-    for (auto& kv : by_nmax) {
-      SizeClass& c = p->pass_classes[i++];
-      items_a.clear();
-      items_b.clear();
-      for (int32_t b : kv.second) {
-        const int32_t na = plans[b].PA;
-        for (int32_t k = 0; k < na; ++k) items_a.push_back(BatchItem{b, k, na});
-        const int32_t nb = (int32_t)pass_b_items(plans[b].nmax, m[b]);
-        for (int32_t k = 0; k < nb; ++k) items_b.push_back(BatchItem{b, k, nb});
-      }
-      ok = ok &&
-           hipMemcpy(at<int32_t>(p, c.probs_off), kv.second.data(), sizeof(int32_t) * kv.second.size(),
-                     hipMemcpyHostToDevice) == hipSuccess &&
-           hipMemcpy(at<BatchItem>(p, c.items_a_off), items_a.data(), sizeof(BatchItem) * items_a.size(),
-                     hipMemcpyHostToDevice) == hipSuccess &&
-           hipMemcpy(at<BatchItem>(p, c.items_b_off), items_b.data(), sizeof(BatchItem) * items_b.size(),
-                     hipMemcpyHostToDevice) == hipSuccess;
-    }
+  auto up = [&](size_t dst, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpy(base + dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  ok = up(p->sk_off, sk.data(), sizeof(SketchArgs) * batch) && up(p->pa_off, pa.data(), sizeof(PassAArgs) * batch) &&
+       up(p->ch_off, ch.data(), sizeof(CholArgs) * batch) && up(p->pb_off, pb.data(), sizeof(PassBArgs) * batch);
+  for (size_t c = 0; ok && c < p->classes.size(); ++c) {
+    const PassClass& pc = p->classes[c];
+    const HostLists& h = lists[c];
+    ok = up(pc.probs_off, h.probs.data(), sizeof(int32_t) * h.probs.size()) &&
+         up(pc.items_g_off, h.g.data(), sizeof(BatchItem) * h.g.size()) &&
+         up(pc.items_a_off, h.a.data(), sizeof(BatchItem) * h.a.size()) &&
+         up(pc.items_b_off, h.b.data(), sizeof(BatchItem) * h.b.size());
+    for (size_t k = 0; ok && k < pc.sketches.size(); ++k)
+      ok = up(pc.sketches[k].probs_off, h.sk[k].data(), sizeof(int32_t) * h.sk[k].size());
   }
   if (!ok) {
-    (void)hipFree(p->dmem);
-    delete p;
+    release(p);
     return RPCHOLQR_EHIP;
   }
   *out = p;
   return RPCHOLQR_OK;
 }
 
-int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, void* stream) {
-  if (!p || !info) return RPCHOLQR_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  int32_t* inf = (int32_t*)info;
+// The chain of one column class on stream st.
+void launch_class(const rpcholqr_batched_plan* p, const PassClass& c, int32_t* inf, hipStream_t st) {
   const SketchArgs* sk = at<SketchArgs>(p, p->sk_off);
   const PassAArgs* pa = at<PassAArgs>(p, p->pa_off);
   const CholArgs* ch = at<CholArgs>(p, p->ch_off);
   const PassBArgs* pb = at<PassBArgs>(p, p->pb_off);
-  // Lines 2-3 of Algorithm rpCholesky-QR for every problem.
-  hipLaunchKernelGGL(kb_gather, dim3((unsigned)p->gather_items), dim3(kGatherThreads), 0, st, sk,
-                     at<BatchItem>(p, p->gather_off));
-  for (const SizeClass& c : p->sketch_classes) {
-    const int32_t* probs = at<int32_t>(p, c.probs_off);
-    const dim3 g((unsigned)c.nprobs), blk(kSketchThreads);
-    switch (c.key) {
-      case 4: hipLaunchKernelGGL((kb_sketch_qr<4>), g, blk, 0, st, sk, probs, inf); break;
-      case 8: hipLaunchKernelGGL((kb_sketch_qr<8>), g, blk, 0, st, sk, probs, inf); break;
-      case 12: hipLaunchKernelGGL((kb_sketch_qr<12>), g, blk, 0, st, sk, probs, inf); break;
-      case 16: hipLaunchKernelGGL((kb_sketch_qr<16>), g, blk, 0, st, sk, probs, inf); break;
-      case 24: hipLaunchKernelGGL((kb_sketch_qr<24>), g, blk, 0, st, sk, probs, inf); break;
-      case 108: hipLaunchKernelGGL((kb_sketch_qr_wide<8>), g, blk, 0, st, sk, probs, inf); break;
-      case 112: hipLaunchKernelGGL((kb_sketch_qr_wide<12>), g, blk, 0, st, sk, probs, inf); break;
-      case 116: hipLaunchKernelGGL((kb_sketch_qr_wide<16>), g, blk, 0, st, sk, probs, inf); break;
-      case 124: hipLaunchKernelGGL((kb_sketch_qr_wide<24>), g, blk, 0, st, sk, probs, inf); break;
+  // Lines 2-3 of Algorithm rpCholesky-QR.
+  hipLaunchKernelGGL(kb_gather, dim3((unsigned)c.items_g), dim3(kGatherThreads), 0, st, sk,
+                     at<BatchItem>(p, c.items_g_off));
+  for (const SketchGroup& g : c.sketches) {
+    const int32_t* probs = at<int32_t>(p, g.probs_off);
+    const dim3 grid((unsigned)g.nprobs), blk(kSketchThreads);
+    switch (g.key) {
+      case 4: hipLaunchKernelGGL((kb_sketch_qr<4>), grid, blk, 0, st, sk, probs, inf); break;
+      case 8: hipLaunchKernelGGL((kb_sketch_qr<8>), grid, blk, 0, st, sk, probs, inf); break;
+      case 12: hipLaunchKernelGGL((kb_sketch_qr<12>), grid, blk, 0, st, sk, probs, inf); break;
+      case 16: hipLaunchKernelGGL((kb_sketch_qr<16>), grid, blk, 0, st, sk, probs, inf); break;
+      case 24: hipLaunchKernelGGL((kb_sketch_qr<24>), grid, blk, 0, st, sk, probs, inf); break;
+      case 108: hipLaunchKernelGGL((kb_sketch_qr_wide<8>), grid, blk, 0, st, sk, probs, inf); break;
+      case 112: hipLaunchKernelGGL((kb_sketch_qr_wide<12>), grid, blk, 0, st, sk, probs, inf); break;
+      case 116: hipLaunchKernelGGL((kb_sketch_qr_wide<16>), grid, blk, 0, st, sk, probs, inf); break;
+      case 124: hipLaunchKernelGGL((kb_sketch_qr_wide<24>), grid, blk, 0, st, sk, probs, inf); break;
       case 0:
-        hipLaunchKernelGGL((kb_sketch_qr_generic<64>), g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs, inf);
-        break;
-      default:
-        hipLaunchKernelGGL((kb_sketch_qr_generic<kWideN>), g, blk, 2 * (size_t)c.max_s * sizeof(double), st, sk, probs,
+        hipLaunchKernelGGL((kb_sketch_qr_generic<64>), grid, blk, 2 * (size_t)g.max_s * sizeof(double), st, sk, probs,
                            inf);
         break;
-    }
-  }
-  if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
-  // Lines 4-8 of Algorithm Preconditioned Cholesky-QR, one launch per column class.
-  for (const SizeClass& c : p->pass_classes) {
-    const BatchItem* it = at<BatchItem>(p, c.items_a_off);
-    const dim3 g((unsigned)c.items_a), blk(kPassThreads);
-    switch (c.key) {
-      case 16: hipLaunchKernelGGL((kb_passA<16>), g, blk, 0, st, pa, it, inf); break;
-      case 32: hipLaunchKernelGGL((kb_passA<32>), g, blk, 0, st, pa, it, inf); break;
-      case 48: hipLaunchKernelGGL((kb_passA<48>), g, blk, 0, st, pa, it, inf); break;
-      case 64: hipLaunchKernelGGL((kb_passA<64>), g, blk, 0, st, pa, it, inf); break;
       default:
-        hipLaunchKernelGGL(kb_passW, g, blk, 0, st, pa, it, inf);
-        hipLaunchKernelGGL(kb_gramW, g, blk, 0, st, pa, it, inf);
+        hipLaunchKernelGGL((kb_sketch_qr_generic<kWideN>), grid, blk, 2 * (size_t)g.max_s * sizeof(double), st, sk,
+                           probs, inf);
         break;
     }
   }
-  for (const SizeClass& c : p->pass_classes) {
-    const int32_t* probs = at<int32_t>(p, c.probs_off);
-    const dim3 g((unsigned)c.nprobs), blk(kCholThreads);
-    switch (c.key) {
-      case 16: hipLaunchKernelGGL((kb_cholesky<16>), g, blk, 0, st, ch, probs, inf); break;
-      case 32: hipLaunchKernelGGL((kb_cholesky<32>), g, blk, 0, st, ch, probs, inf); break;
-      case 48: hipLaunchKernelGGL((kb_cholesky<48>), g, blk, 0, st, ch, probs, inf); break;
-      case 64: hipLaunchKernelGGL((kb_cholesky<64>), g, blk, 0, st, ch, probs, inf); break;
-      default: hipLaunchKernelGGL((kb_cholesky<kWideN>), g, blk, 0, st, ch, probs, inf); break;
-    }
+  // Lines 4-8 of Algorithm Preconditioned Cholesky-QR.
+  const BatchItem* ia = at<BatchItem>(p, c.items_a_off);
+  const BatchItem* ib = at<BatchItem>(p, c.items_b_off);
+  const int32_t* probs = at<int32_t>(p, c.probs_off);
+  const dim3 ga((unsigned)c.items_a), gc((unsigned)c.nprobs), gb((unsigned)c.items_b);
+  const dim3 bp(kPassThreads), bc(kCholThreads), bb(kPassBThreads);
+  switch (c.nmax) {
+    case 16:
+      hipLaunchKernelGGL((kb_passA<16>), ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL((kb_cholesky<16>), gc, bc, 0, st, ch, probs, inf);
+      hipLaunchKernelGGL((kb_passB<16>), gb, bb, 0, st, pb, ib, inf);
+      break;
+    case 32:
+      hipLaunchKernelGGL((kb_passA<32>), ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL((kb_cholesky<32>), gc, bc, 0, st, ch, probs, inf);
+      hipLaunchKernelGGL((kb_passB<32>), gb, bb, 0, st, pb, ib, inf);
+      break;
+    case 48:
+      hipLaunchKernelGGL((kb_passA<48>), ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL((kb_cholesky<48>), gc, bc, 0, st, ch, probs, inf);
+      hipLaunchKernelGGL((kb_passB<48>), gb, bb, 0, st, pb, ib, inf);
+      break;
+    case 64:
+      hipLaunchKernelGGL((kb_passA<64>), ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL((kb_cholesky<64>), gc, bc, 0, st, ch, probs, inf);
+      hipLaunchKernelGGL((kb_passB<64>), gb, bb, 0, st, pb, ib, inf);
+      break;
+    default:
+      hipLaunchKernelGGL(kb_passW, ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL(kb_gramW, ga, bp, 0, st, pa, ia, inf);
+      hipLaunchKernelGGL((kb_cholesky<kWideN>), gc, bc, 0, st, ch, probs, inf);
+      hipLaunchKernelGGL(kb_passB128, gb, dim3(kPassB128Threads), 0, st, pb, ib, inf);
+      break;
   }
-  for (const SizeClass& c : p->pass_classes) {
-    const BatchItem* it = at<BatchItem>(p, c.items_b_off);
-    const dim3 g((unsigned)c.items_b), blk(kPassBThreads);
-    switch (c.key) {
-      case 16: hipLaunchKernelGGL((kb_passB<16>), g, blk, 0, st, pb, it, inf); break;
-      case 32: hipLaunchKernelGGL((kb_passB<32>), g, blk, 0, st, pb, it, inf); break;
-      case 48: hipLaunchKernelGGL((kb_passB<48>), g, blk, 0, st, pb, it, inf); break;
-      case 64: hipLaunchKernelGGL((kb_passB<64>), g, blk, 0, st, pb, it, inf); break;
-      default: hipLaunchKernelGGL(kb_passB128, g, dim3(kPassB128Threads), 0, st, pb, it, inf); break;
-    }
+}
+
+// The column classes run concurrently: the first on the caller's stream, the
+// others on the plan's streams, forked from and joined to the caller's stream
+// by events (both are recorded by a stream capture).  Classes with the most
+// work start first.
+int32_t batched_execute(const rpcholqr_batched_plan* p, rpcholqr_info* info, void* stream) {
+  if (!p || !info) return RPCHOLQR_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int32_t* inf = (int32_t*)info;
+  const size_t nc = p->classes.size();
+  if (nc > 1) {
+    if (hipEventRecord(p->fork, st) != hipSuccess) return RPCHOLQR_EHIP;
+    for (size_t c = 1; c < nc; ++c)
+      if (hipStreamWaitEvent(p->streams[c - 1], p->fork, 0) != hipSuccess) return RPCHOLQR_EHIP;
   }
+  for (size_t c = 0; c < nc; ++c) launch_class(p, p->classes[c], inf, c == 0 ? st : p->streams[c - 1]);
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+  for (size_t c = 1; c < nc; ++c) {
+    if (hipEventRecord(p->joins[c - 1], p->streams[c - 1]) != hipSuccess) return RPCHOLQR_EHIP;
+    if (hipStreamWaitEvent(st, p->joins[c - 1], 0) != hipSuccess) return RPCHOLQR_EHIP;
+  }
+  return RPCHOLQR_OK;
+}
+
+int32_t set_tuning(const rpcholqr_batched_tuning* entries, int32_t count) {
+  if (count < 0 || (count > 0 && !entries)) return RPCHOLQR_EINVAL;
+  std::vector<TuneEntry> t;
+  for (int32_t i = 0; i < count; ++i) {
+    const rpcholqr_batched_tuning& e = entries[i];
+    const bool nmax_ok = e.nmax == 16 || e.nmax == 32 || e.nmax == 48 || e.nmax == 64 || e.nmax == kWideN;
+    if (!nmax_ok || e.m_max < 1 || e.pa_rows < kPassWaves * kWave || e.pa_rows % (kPassWaves * kWave) != 0 ||
+        e.pa_max < 1 || e.pa_max > kBatchMaxPartials || e.pb_rows < 16 || e.pb_rows % 16 != 0)
+      return RPCHOLQR_EINVAL;
+    TuneEntry x;
+    x.nmax = e.nmax;
+    x.m_max = e.m_max;
+    x.pa_rows = e.pa_rows;
+    x.pa_max = e.pa_max;
+    x.pb_rows = e.pb_rows;
+    t.push_back(x);
+  }
+  std::stable_sort(t.begin(), t.end(), [](const TuneEntry& x, const TuneEntry& y) {
+    return x.nmax != y.nmax ? x.nmax < y.nmax : x.m_max < y.m_max;
+  });
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune = std::move(t);
   return RPCHOLQR_OK;
 }
 
@@ -1136,9 +1233,12 @@ size_t rpcholqr_batched_plan_device_bytes(const rpcholqr_batched_plan* plan) { r
 
 int32_t rpcholqr_batched_plan_destroy(rpcholqr_batched_plan* plan) {
   if (!plan) return RPCHOLQR_OK;
-  const bool ok = plan->dmem == nullptr || hipFree(plan->dmem) == hipSuccess;
-  delete plan;
-  return ok ? RPCHOLQR_OK : RPCHOLQR_EHIP;
+  release(plan);
+  return RPCHOLQR_OK;
+}
+
+int32_t rpcholqr_batched_set_tuning(const rpcholqr_batched_tuning* entries, int32_t count) {
+  return set_tuning(entries, count);
 }
 
 int32_t rpcholqr_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, const int64_t* s,

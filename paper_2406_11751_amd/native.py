@@ -34,6 +34,7 @@ SIGNATURES = {
     "rpcholqr_batched_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
                                             ctypes.POINTER(_vp), ctypes.POINTER(_i64)]),
     "rpcholqr_batched_execute": (_i32, [_vp, _vp, _vp]),
+    "rpcholqr_batched_set_tuning": (_i32, [_vp, _i32]),
     "rpcholqr_batched_plan_device_bytes": (_sz, [_vp]),
     "rpcholqr_batched_plan_destroy": (_i32, [_vp]),
     "rpcholqr_factor_batched": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
@@ -179,6 +180,37 @@ def factor(A, s: int, seed: int, *, Q=None, R=None, workspace=None, info=None, s
     return (Q, R, info, extra) if debug else (Q, R, info)
 
 
+def factor_noalloc(A, s: int, seed: int, *, Q=None, R=None, info=None, stream=None, precision: int = FP64,
+                   check: bool = True):
+    """rpcholqr_factor_noalloc: as factor(), with the workspace in the library's
+    static device array (nothing is allocated by the call).  Returns (Q, R, info)."""
+    import torch
+
+    lib = load_library()
+    m, n = A.shape
+    dev = A.device
+    lda = _ld(A, m)
+    if Q is None:
+        Q = colmajor_empty(m, n, dev)
+    if R is None:
+        R = colmajor_empty(n, n, dev)
+    ldq, ldr = _ld(Q, m), _ld(R, n)
+    if info is None:
+        info = torch.empty(2, dtype=torch.int32, device=dev)
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib.rpcholqr_factor_noalloc(m, n, s, seed & (2**64 - 1), _ptr(A), lda, _ptr(Q), ldq, _ptr(R), ldr,
+                                     precision, _ptr(info), st)
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_factor_noalloc returned {STATUS.get(rc, rc)}", status=rc)
+    if check:
+        torch.cuda.synchronize(dev)
+        code, index = (int(v) for v in info.cpu().tolist())
+        if code != 0:
+            raise RpCholQRError(f"numerical failure {INFO.get(code, code)} at column {index}", code=code,
+                                index=index)
+    return Q, R, info
+
+
 def precond_factor(A, Rs, *, Q=None, R=None, workspace=None, info=None, stream=None, precision: int = FP64,
                    check: bool = True):
     """Algorithm "Preconditioned Cholesky-QR" with the given n x n upper
@@ -230,6 +262,44 @@ def sample_indices(m: int, s: int, seed: int):
     return idx
 
 
+class BatchedTuning(ctypes.Structure):
+    """rpcholqr_batched_tuning (include/rpcholqr.h)."""
+
+    _fields_ = [("nmax", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("m_max", ctypes.c_int64),
+                ("pa_rows", ctypes.c_int32), ("pa_max", ctypes.c_int32), ("pb_rows", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
+
+
+TUNING_PATH = os.path.join(HERE, "tuning", "batched_mi355x.json")
+_tuning_installed = False
+
+
+def set_batched_tuning(entries) -> None:
+    """Installs the batched launch-shape table (a list of dicts with keys nmax,
+    m_max, pa_rows, pa_max, pb_rows); an empty list restores the built-in shapes."""
+    global _tuning_installed
+    arr = (BatchedTuning * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        arr[i] = BatchedTuning(int(e["nmax"]), 0, int(e["m_max"]), int(e["pa_rows"]), int(e["pa_max"]),
+                               int(e["pb_rows"]), 0)
+    rc = load_library().rpcholqr_batched_set_tuning(ctypes.cast(arr, ctypes.c_void_p), len(entries))
+    if rc != 0:
+        raise RpCholQRError(f"rpcholqr_batched_set_tuning returned {STATUS.get(rc, rc)}", status=rc)
+    _tuning_installed = True
+
+
+def load_batched_tuning(path: str = TUNING_PATH) -> bool:
+    """Installs the table the autotuner wrote (paper_2406_11751_amd/autotune.py), if
+    the file exists.  Returns whether a table was installed."""
+    import json
+
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        set_batched_tuning(json.load(f)["entries"])
+    return True
+
+
 class BatchedPlan:
     """A batch of independent factorizations planned once and executed any
     number of times (rpcholqr_batched_plan_*).  The plan keeps references to the
@@ -239,6 +309,8 @@ class BatchedPlan:
         import torch
 
         lib = load_library()
+        if not _tuning_installed:
+            load_batched_tuning()
         b = len(As)
         if b < 1:
             raise ValueError("empty batch")

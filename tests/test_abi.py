@@ -103,3 +103,21 @@ def test_bench_rejects_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_batched_tuning_table_is_well_formed():
+    """The autotuner's committed table (if present) has one entry per column
+    class and m bucket, with shapes the library accepts."""
+    import json
+    import os
+
+    import paper_2406_11751_amd as rq
+
+    path = rq.native.TUNING_PATH
+    if not os.path.exists(path):
+        return
+    t = json.load(open(path))
+    for e in t["entries"]:
+        assert e["nmax"] in (16, 32, 48, 64, 128)
+        assert e["pa_rows"] % 256 == 0 and 1 <= e["pa_max"] <= 128 and e["pb_rows"] % 16 == 0
+    assert {e["nmax"] for e in t["entries"]} == {16, 32, 48, 64, 128}

@@ -235,3 +235,36 @@ def test_batched_config3_like_sample():
             ref = oracle.rpcholqr(As_h[i], 3 * int(ns[i]), i, nthreads=NTHREADS)
             assert metrics.rel_fro(Qh, ref.Q) < TOL and metrics.rel_fro(Rh, ref.R) < TOL
     plan.close()
+
+
+def test_batched_tuning_shapes_agree():
+    """Launch shapes from rpcholqr_batched_set_tuning: one Gram partial and
+    16-row pass-B workgroups for the 64-column class, many small partials for the
+    128-column class; every problem still matches the oracle, and a malformed
+    table is rejected without changing the installed one."""
+    probs = [(30000, 64, 192, 1e10), (45000, 100, 300, 1e8), (2100, 20, 60, 1e12), (70000, 128, 384, 1e6)]
+    As_h = [gen_usv(m, n, k, 900 + i) for i, (m, n, s, k) in enumerate(probs)]
+    As = [dev(A) for A in As_h]
+    ss = [p[2] for p in probs]
+    refs = [oracle.rpcholqr(A, p[2], 21 + i, nthreads=NTHREADS) for i, (A, p) in enumerate(zip(As_h, probs))]
+    announce("batched tuning shapes")
+    table = [dict(nmax=64, m_max=10**9, pa_rows=256, pa_max=1, pb_rows=16),
+             dict(nmax=128, m_max=50000, pa_rows=512, pa_max=128, pb_rows=4096),
+             dict(nmax=128, m_max=10**9, pa_rows=16384, pa_max=3, pb_rows=32),
+             dict(nmax=32, m_max=10**9, pa_rows=256, pa_max=128, pb_rows=64)]
+    try:
+        rq().set_batched_tuning(table)
+        with pytest.raises(rq().RpCholQRError):
+            rq().set_batched_tuning([dict(nmax=40, m_max=10, pa_rows=256, pa_max=1, pb_rows=16)])
+        with pytest.raises(rq().RpCholQRError):
+            rq().set_batched_tuning([dict(nmax=64, m_max=10, pa_rows=300, pa_max=1, pb_rows=16)])
+        with pytest.raises(rq().RpCholQRError):
+            rq().set_batched_tuning([dict(nmax=64, m_max=10, pa_rows=256, pa_max=129, pb_rows=16)])
+        plan = rq().BatchedPlan(As, ss, [21 + i for i in range(len(As))])
+        plan.execute()
+        for i, ref in enumerate(refs):
+            assert metrics.rel_fro(host(plan.Qs[i]), ref.Q) < TOL and metrics.rel_fro(host(plan.Rs[i]), ref.R) < TOL
+        plan.close()
+    finally:
+        rq().set_batched_tuning([])
+        rq().load_batched_tuning()
