@@ -68,6 +68,32 @@ def counter_per_dispatch(root: str, counter: str):
     return {k: (len(ids[k]), total[k] / len(ids[k])) for k in total}
 
 
+def counter_by_kernel(root: str, counter: str):
+    """{kernel name: mean of the counter over its dispatches}."""
+    rows = list(csv.DictReader(open(_one("*counter_collection.csv", root))))
+    vals = collections.defaultdict(list)
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def mfma_summary(stats_dir, mfma_dir, workload, command_stats, command_mfma, out_path):
+    """Markdown table of the library's kernels: calls, average time, and the
+    derived MfmaUtil counter (MFMA busy cycles over active cycles of all SIMDs)."""
+    stats = [s for s in kernel_stats(stats_dir) if "rpq::" in s["name"]]
+    util = counter_by_kernel(mfma_dir, "MfmaUtil")
+    lines = [f"# rocprofv3: {workload}", "", "Kernel statistics and MFMA utilization, commands (repository root, MI355X):",
+             "", "```", command_stats, command_mfma, "```", "",
+             "| kernel | calls | average us | total ms | MfmaUtil % |", "|---|---|---|---|---|"]
+    for s in sorted(stats, key=lambda s: -s["avg_us"] * s["calls"]):
+        u = util.get(s["name"])
+        lines.append(f"| `{s['name']}` | {s['calls']} | {s['avg_us']:.1f} | {s['avg_us'] * s['calls'] / 1e3:.2f} | "
+                     + (f"{u:.1f}" if u is not None else "-") + " |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def _pick(table: dict, needle: str):
     keys = [k for k in table if needle in k]
     if not keys:
@@ -77,6 +103,8 @@ def _pick(table: dict, needle: str):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mfma", default=None,
+                    help="MfmaUtil counter run: write only a kernel table with MFMA utilization to --out/--tag.md")
     ap.add_argument("--stats", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
@@ -90,10 +118,22 @@ def main():
     ap.add_argument("--command-fetch", required=True)
     ap.add_argument("--command-write", required=True)
     ap.add_argument("--command-copy", required=True)
+    ap.add_argument("--command-mfma", default="")
     ap.add_argument("--algorithmic-bytes", type=float, required=True,
                     help="bytes the kernel must move per launch (for comparison)")
     ap.add_argument("--out", required=True)
+    if "--mfma" in os.sys.argv:
+        for req in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel", "--command-fetch",
+                    "--command-write", "--command-copy", "--algorithmic-bytes"):
+            for act in ap._actions:
+                if req in act.option_strings:
+                    act.required = False
     a = ap.parse_args()
+    if a.mfma:
+        os.makedirs(a.out, exist_ok=True)
+        mfma_summary(a.stats, a.mfma, a.workload, a.command_stats, a.command_mfma,
+                     os.path.join(a.out, f"{a.tag}.md"))
+        return
 
     stats = kernel_stats(a.stats)
     lib = [s for s in stats if "rpq::" in s["name"]]
