@@ -67,6 +67,17 @@ def lib():
         L.orc_rpcholqr.restype = i32
         L.orc_rpcholqr.argtypes = [i64, i64, i64, u64, dp, i64, dp, i64, dp, i64,
                                    dp, dp, dp, dp, dp, dp, dp, i32]
+        L.orc_rpcholqr_ex.restype = i32
+        L.orc_rpcholqr_ex.argtypes = [i64, i64, i64, u64, i32, dp, i64, dp, i64, dp, i64,
+                                      dp, dp, dp, dp, dp, dp, dp, i32]
+        L.orc_smooth_sample.restype = None
+        L.orc_smooth_sample.argtypes = [i64, i64, i64, u64, dp, i64, dp, dp, i32]
+        L.orc_smooth_rows.restype = i64
+        L.orc_smooth_rows.argtypes = [i64]
+        L.orc_smooth_chunk_rows.restype = i64
+        L.orc_smooth_chunk_rows.argtypes = [i64]
+        L.orc_rademacher.restype = ctypes.c_double
+        L.orc_rademacher.argtypes = [u64, i64]
         L.orc_max_threads.restype = i32
         L.orc_max_threads.argtypes = []
         _lib = L
@@ -172,8 +183,31 @@ def alg1(A: np.ndarray, Rs: np.ndarray, nthreads: int = 1, keep: bool = True) ->
     return Result(Q=Q, R=R, A1=A1, G1=G1, R2=R2, status=rc, index=bad.value)
 
 
-def rpcholqr(A: np.ndarray, s: int, seed: int, nthreads: int = 1, keep: bool = True) -> Result:
-    """Algorithm "rpCholesky-QR" (Section 4) with F = I.
+def smooth_rows(m: int) -> int:
+    return int(lib().orc_smooth_rows(m))
+
+
+def smooth_chunk_rows(m: int) -> int:
+    return int(lib().orc_smooth_chunk_rows(m))
+
+
+def rademacher(seed: int, i: int) -> float:
+    return float(lib().orc_rademacher(seed & (2**64 - 1), i))
+
+
+def smooth_sample(A: np.ndarray, s: int, seed: int, nthreads: int = 1):
+    """Smoothed sample (Algorithm rpCholesky-QR line 2, F = H D): (idx, As)."""
+    A = _f64(A)
+    m, n = A.shape
+    idx = np.empty(s, dtype=np.int64)
+    As = np.empty((s, n), dtype=np.float64, order="F")
+    lib().orc_smooth_sample(m, n, s, seed & (2**64 - 1), _p(A), max(m, 1), _p(idx), _p(As), nthreads)
+    return idx, As
+
+
+def rpcholqr(A: np.ndarray, s: int, seed: int, nthreads: int = 1, keep: bool = True,
+             smooth: bool = False) -> Result:
+    """Algorithm "rpCholesky-QR" (Section 4); F = I, or F = H D with smooth=True.
 
     Returns Q, R and the intermediates idx, As, Rs, A1 (if keep), G1, R2, plus
     status (OK / ESKETCH / ECHOL / EINVAL) and the failing index.
@@ -189,7 +223,7 @@ def rpcholqr(A: np.ndarray, s: int, seed: int, nthreads: int = 1, keep: bool = T
     G1 = np.empty((n, n), dtype=np.float64, order="F")
     R2 = np.empty((n, n), dtype=np.float64, order="F")
     bad = ctypes.c_int32(-1)
-    rc = lib().orc_rpcholqr(m, n, s, seed & (2**64 - 1), _p(A), max(m, 1),
-                            _p(Q), max(m, 1), _p(R), n, _p(idx), _p(As), _p(Rs), _p(A1), _p(G1),
-                            _p(R2), ctypes.addressof(bad), nthreads)
+    rc = lib().orc_rpcholqr_ex(m, n, s, seed & (2**64 - 1), 1 if smooth else 0, _p(A), max(m, 1),
+                               _p(Q), max(m, 1), _p(R), n, _p(idx), _p(As), _p(Rs), _p(A1), _p(G1),
+                               _p(R2), ctypes.addressof(bad), nthreads)
     return Result(Q=Q, R=R, idx=idx, As=As, Rs=Rs, A1=A1, G1=G1, R2=R2, status=rc, index=bad.value)

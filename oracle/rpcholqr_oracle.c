@@ -25,7 +25,9 @@
  *       line 8  R  = R2 R_s       -> orc_trmm_upper
  *
  * Readings where the paper is silent (each is also listed in the design notes):
- *  - The smoothing matrix F is the identity (rows of A are sampled directly).
+ *  - The smoothing matrix F is the identity (rows of A are sampled directly),
+ *    or, on request, F = H D with a Walsh-Hadamard H on A padded to a power of
+ *    two rows (orc_smooth_sample).
  *  - Row indices come from SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in
  *    counter form, z_r = mix64(seed + (r+1)*0x9e3779b97f4a7c15), reduced to [0,m)
  *    by a 64x64->128-bit multiply-high (Lemire, ACM TOMACS 2019).  0-based.
@@ -83,6 +85,70 @@ void orc_gather(int64_t m, int64_t n, int64_t s, const int64_t* idx, const doubl
   const double c = sqrt((double)m / (double)s);
   for (int64_t j = 0; j < n; ++j)
     for (int64_t r = 0; r < s; ++r) AT(As, s, r, j) = c * AT(A, lda, idx[r], j);
+}
+
+/* ---------------------------------------------------------------------------
+ * Smoothed sample (Algorithm rpCholesky-QR line 2 with F = F_T D; the remark
+ * after Theorem t_prob: F_T a Walsh-Hadamard transform, D a diagonal of
+ * independent random signs).  A is padded with zero rows to M = 2^p >= m rows;
+ * F = H D with H(k, i) = (-1)^popcount(k AND i) / sqrt(M) (Sylvester order) is
+ * orthogonal on R^M, and only the c sampled rows of F [A; 0] are formed:
+ *   A_s(r, j) = sqrt(M/c) (F [A;0])(idx_r, j) = T(r, j) / sqrt(c),
+ *   T(r, j)   = sum_{i < m} D_i (-1)^popcount(idx_r AND i) A(i, j),
+ * with idx_r uniform on [0, M) (orc_sample_indices with M).  Every term is an
+ * exact signed copy of A(i, j); the order of the sum is fixed:
+ *   rows are cut into chunks of G * 4096 consecutive rows, G = max(1,
+ *   ceil(ceil(m / 4096) / 256)) (so at most 256 chunks); within a chunk the
+ *   terms are accumulated with fma in ascending i starting from 0; the chunk
+ *   sums are then added in ascending chunk order (T = P_0, T = T + P_1, ...);
+ *   finally A_s = T * (1 / sqrt(c)) with both operations correctly rounded.
+ * D_i = +1 if bit 63 of SplitMix64 output i of the generator seeded with
+ * (seed XOR ORC_SIGN_SALT) is 0, else -1. */
+#define ORC_SIGN_SALT 0x5851f42d4c957f2dull
+#define ORC_SMOOTH_BLOCK 4096
+
+int64_t orc_smooth_rows(int64_t m) {
+  int64_t M = 1;
+  while (M < m) M <<= 1;
+  return M;
+}
+
+int64_t orc_smooth_chunk_rows(int64_t m) {
+  const int64_t blocks = (m + ORC_SMOOTH_BLOCK - 1) / ORC_SMOOTH_BLOCK;
+  int64_t g = (blocks + 255) / 256;
+  if (g < 1) g = 1;
+  return g * ORC_SMOOTH_BLOCK;
+}
+
+double orc_rademacher(uint64_t seed, int64_t i) {
+  return (orc_splitmix64_at(seed ^ ORC_SIGN_SALT, (uint64_t)i) >> 63) ? -1.0 : 1.0;
+}
+
+/* Smoothed sample: idx[s] in [0, M) and As (s x n, ld s). */
+void orc_smooth_sample(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
+                       int64_t* idx, double* As, int nthreads) {
+  const int64_t M = orc_smooth_rows(m), chunk = orc_smooth_chunk_rows(m);
+  const double sc = 1.0 / sqrt((double)s);
+  double* D = (double*)malloc((size_t)m * sizeof(double));
+  orc_sample_indices(M, s, seed, idx);
+  for (int64_t i = 0; i < m; ++i) D[i] = orc_rademacher(seed, i);
+#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t r = 0; r < s; ++r) {
+      const uint64_t k = (uint64_t)idx[r];
+      double T = 0.0;
+      for (int64_t c0 = 0; c0 < m; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < m ? c0 + chunk : m;
+        double p = 0.0;
+        for (int64_t i = c0; i < c1; ++i) {
+          const double sg = (__builtin_popcountll(k & (uint64_t)i) & 1) ? -D[i] : D[i];
+          p = fma(sg, AT(A, lda, i, j), p);
+        }
+        T = (c0 == 0) ? p : T + p;
+      }
+      AT(As, s, r, j) = T * sc;
+    }
+  free(D);
 }
 
 /* ---------------------------------------------------------------------------
@@ -262,10 +328,25 @@ int orc_alg1(int64_t m, int64_t n, const double* A, int64_t lda, const double* R
  * A1 (m x n, ld m), G1 and R2 (n x n, ld n).
  * Returns ORC_OK, ORC_EINVAL, ORC_ESKETCH or ORC_ECHOL; *info_index gets the
  * failing column for the last two. */
+int orc_rpcholqr_ex(int64_t m, int64_t n, int64_t s, uint64_t seed, int smooth, const double* A, int64_t lda,
+                    double* Q, int64_t ldq, double* R, int64_t ldr, int64_t* idx_out, double* As_out,
+                    double* Rs_out, double* A1_out, double* G1_out, double* R2_out, int32_t* info_index,
+                    int nthreads);
+
 int orc_rpcholqr(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
                  double* Q, int64_t ldq, double* R, int64_t ldr, int64_t* idx_out, double* As_out,
                  double* Rs_out, double* A1_out, double* G1_out, double* R2_out, int32_t* info_index,
                  int nthreads) {
+  return orc_rpcholqr_ex(m, n, s, seed, 0, A, lda, Q, ldq, R, ldr, idx_out, As_out, Rs_out, A1_out, G1_out,
+                         R2_out, info_index, nthreads);
+}
+
+/* As orc_rpcholqr; with smooth != 0 the sample is the smoothed one
+ * (orc_smooth_sample) instead of A's own rows. */
+int orc_rpcholqr_ex(int64_t m, int64_t n, int64_t s, uint64_t seed, int smooth, const double* A, int64_t lda,
+                    double* Q, int64_t ldq, double* R, int64_t ldr, int64_t* idx_out, double* As_out,
+                    double* Rs_out, double* A1_out, double* G1_out, double* R2_out, int32_t* info_index,
+                    int nthreads) {
   int rc;
   int64_t* idx;
   double *As, *Rs;
@@ -274,8 +355,12 @@ int orc_rpcholqr(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A
   idx = idx_out ? idx_out : (int64_t*)malloc((size_t)s * sizeof(int64_t));
   As = (double*)malloc((size_t)s * (size_t)n * sizeof(double));
   Rs = Rs_out ? Rs_out : (double*)malloc((size_t)n * (size_t)n * sizeof(double));
-  orc_sample_indices(m, s, seed, idx);          /* line 2: which rows */
-  orc_gather(m, n, s, idx, A, lda, As);         /* line 2: scaled sample */
+  if (smooth) {
+    orc_smooth_sample(m, n, s, seed, A, lda, idx, As, nthreads); /* line 2, F = F_T D */
+  } else {
+    orc_sample_indices(m, s, seed, idx);        /* line 2: which rows */
+    orc_gather(m, n, s, idx, A, lda, As);       /* line 2: scaled sample (F = I) */
+  }
   if (As_out) memcpy(As_out, As, (size_t)s * (size_t)n * sizeof(double));
   rc = orc_householder_r(s, n, As, s, Rs, n, info_index); /* line 3 */
   if (rc == ORC_OK) {
