@@ -76,6 +76,8 @@ def lib():
         L.orc_smooth_rows.argtypes = [i64]
         L.orc_smooth_chunk_rows.restype = i64
         L.orc_smooth_chunk_rows.argtypes = [i64]
+        L.orc_scramble.restype = u64
+        L.orc_scramble.argtypes = [u64, i64]
         L.orc_rademacher.restype = ctypes.c_double
         L.orc_rademacher.argtypes = [u64, i64]
         L.orc_max_threads.restype = i32
@@ -191,12 +193,16 @@ def smooth_chunk_rows(m: int) -> int:
     return int(lib().orc_smooth_chunk_rows(m))
 
 
+def scramble(i: int, M: int) -> int:
+    return int(lib().orc_scramble(i, M))
+
+
 def rademacher(seed: int, i: int) -> float:
     return float(lib().orc_rademacher(seed & (2**64 - 1), i))
 
 
 def smooth_sample(A: np.ndarray, s: int, seed: int, nthreads: int = 1):
-    """Smoothed sample (Algorithm rpCholesky-QR line 2, F = H D): (idx, As)."""
+    """Smoothed sample (Algorithm rpCholesky-QR line 2, F = H D P): (idx, As)."""
     A = _f64(A)
     m, n = A.shape
     idx = np.empty(s, dtype=np.int64)
@@ -207,7 +213,7 @@ def smooth_sample(A: np.ndarray, s: int, seed: int, nthreads: int = 1):
 
 def rpcholqr(A: np.ndarray, s: int, seed: int, nthreads: int = 1, keep: bool = True,
              smooth: bool = False) -> Result:
-    """Algorithm "rpCholesky-QR" (Section 4); F = I, or F = H D with smooth=True.
+    """Algorithm "rpCholesky-QR" (Section 4); F = I, or F = H D P with smooth=True.
 
     Returns Q, R and the intermediates idx, As, Rs, A1 (if keep), G1, R2, plus
     status (OK / ESKETCH / ECHOL / EINVAL) and the failing index.

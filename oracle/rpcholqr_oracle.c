@@ -91,10 +91,15 @@ void orc_gather(int64_t m, int64_t n, int64_t s, const int64_t* idx, const doubl
  * Smoothed sample (Algorithm rpCholesky-QR line 2 with F = F_T D; the remark
  * after Theorem t_prob: F_T a Walsh-Hadamard transform, D a diagonal of
  * independent random signs).  A is padded with zero rows to M = 2^p >= m rows;
- * F = H D with H(k, i) = (-1)^popcount(k AND i) / sqrt(M) (Sylvester order) is
+ * F = H D P with H(k, q) = (-1)^popcount(k AND q) / sqrt(M) (Sylvester order)
+ * and P the permutation moving row i to position pi(i) (orc_scramble) is
  * orthogonal on R^M, and only the c sampled rows of F [A; 0] are formed:
  *   A_s(r, j) = sqrt(M/c) (F [A;0])(idx_r, j) = T(r, j) / sqrt(c),
- *   T(r, j)   = sum_{i < m} D_i (-1)^popcount(idx_r AND i) A(i, j),
+ *   T(r, j)   = sum_{i < m} D_i (-1)^popcount(idx_r AND pi(i)) A(i, j),
+ * (D indexed by the row of A, a relabeling of the independent signs).  Without
+ * P, rows k and k' of F A agree whenever k = k' mod 2^q and A lives in its
+ * first 2^q rows, which makes the sampled matrix singular for such coherent
+ * inputs; pi spreads every bit of i over all p bits.
  * with idx_r uniform on [0, M) (orc_sample_indices with M).  Every term is an
  * exact signed copy of A(i, j); the order of the sum is fixed:
  *   rows are cut into chunks of G * 4096 consecutive rows, G = max(1,
@@ -111,6 +116,20 @@ int64_t orc_smooth_rows(int64_t m) {
   int64_t M = 1;
   while (M < m) M <<= 1;
   return M;
+}
+
+/* pi(i) on p-bit integers (M = 2^p): multiply by an odd constant, xorshift,
+ * multiply, xorshift, all mod M; each step is a bijection of [0, M). */
+uint64_t orc_scramble(uint64_t i, int64_t M) {
+  const uint64_t mask = (uint64_t)M - 1u;
+  int p = 0;
+  while (((int64_t)1 << p) < M) ++p;
+  const int h = p / 2 > 1 ? p / 2 : 1;
+  uint64_t x = (i * 0x9e3779b97f4a7c15ull) & mask;
+  x ^= x >> h;
+  x = (x * 0xbf58476d1ce4e5b9ull) & mask;
+  x ^= x >> h;
+  return x;
 }
 
 int64_t orc_smooth_chunk_rows(int64_t m) {
@@ -130,8 +149,12 @@ void orc_smooth_sample(int64_t m, int64_t n, int64_t s, uint64_t seed, const dou
   const int64_t M = orc_smooth_rows(m), chunk = orc_smooth_chunk_rows(m);
   const double sc = 1.0 / sqrt((double)s);
   double* D = (double*)malloc((size_t)m * sizeof(double));
+  uint64_t* pi = (uint64_t*)malloc((size_t)m * sizeof(uint64_t));
   orc_sample_indices(M, s, seed, idx);
-  for (int64_t i = 0; i < m; ++i) D[i] = orc_rademacher(seed, i);
+  for (int64_t i = 0; i < m; ++i) {
+    D[i] = orc_rademacher(seed, i);
+    pi[i] = orc_scramble((uint64_t)i, M);
+  }
 #pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
   for (int64_t j = 0; j < n; ++j)
     for (int64_t r = 0; r < s; ++r) {
@@ -141,7 +164,7 @@ void orc_smooth_sample(int64_t m, int64_t n, int64_t s, uint64_t seed, const dou
         const int64_t c1 = c0 + chunk < m ? c0 + chunk : m;
         double p = 0.0;
         for (int64_t i = c0; i < c1; ++i) {
-          const double sg = (__builtin_popcountll(k & (uint64_t)i) & 1) ? -D[i] : D[i];
+          const double sg = (__builtin_popcountll(k & pi[i]) & 1) ? -D[i] : D[i];
           p = fma(sg, AT(A, lda, i, j), p);
         }
         T = (c0 == 0) ? p : T + p;
@@ -149,6 +172,7 @@ void orc_smooth_sample(int64_t m, int64_t n, int64_t s, uint64_t seed, const dou
       AT(As, s, r, j) = T * sc;
     }
   free(D);
+  free(pi);
 }
 
 /* ---------------------------------------------------------------------------

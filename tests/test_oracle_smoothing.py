@@ -3,12 +3,15 @@ F = F_T D: the remark after Theorem t_prob allows a Walsh-Hadamard F_T, D a
 diagonal of independent random signs) against its definition, written here
 independently of the oracle:
 
-  M = smallest power of two >= m; H(k, i) = (-1)^popcount(k AND i) (Sylvester
-  order); D_i = +1 if bit 63 of SplitMix64 output i seeded with
-  seed XOR 0x5851f42d4c957f2d is 0, else -1; F = H D / sqrt(M) acts on A padded
-  with zero rows; idx_r uniform on [0, M) (the pinned sampler with M);
+  M = smallest power of two >= m = 2^p; H(k, q) = (-1)^popcount(k AND q)
+  (Sylvester order); pi(i) = the bijection of [0, M): x = i * 0x9e3779b97f4a7c15,
+  x ^= x >> h, x *= 0xbf58476d1ce4e5b9, x ^= x >> h, everything mod M,
+  h = max(1, floor(p / 2)); D_i = +1 if bit 63 of SplitMix64 output i seeded with
+  seed XOR 0x5851f42d4c957f2d is 0, else -1; row i of A padded with zero rows
+  goes to position pi(i) and is multiplied by D_i; F = H / sqrt(M) then mixes;
+  idx_r uniform on [0, M) (the pinned sampler with M);
   A_s = sqrt(M/c) (F [A; 0])(idx, :), computed as T / sqrt(c) with
-  T(r, j) = sum_i D_i (-1)^popcount(idx_r AND i) A(i, j) summed in one fixed
+  T(r, j) = sum_i D_i (-1)^popcount(idx_r AND pi(i)) A(i, j) summed in one fixed
   order: chunks of G * 4096 rows (G = max(1, ceil(ceil(m / 4096) / 256))),
   an fma chain in ascending i within a chunk, chunks added in ascending order,
   then T * (1 / sqrt(c)).
@@ -32,6 +35,16 @@ def splitmix64(seed, r):
     return z ^ (z >> 31)
 
 
+def scramble(i, M):
+    p = M.bit_length() - 1
+    h = max(1, p // 2)
+    x = (i * 0x9E3779B97F4A7C15) % M
+    x ^= x >> h
+    x = (x * 0xBF58476D1CE4E5B9) % M
+    x ^= x >> h
+    return x
+
+
 def signs(seed, m):
     return np.array([-1.0 if splitmix64(seed ^ 0x5851F42D4C957F2D, i) >> 63 else 1.0 for i in range(m)])
 
@@ -40,17 +53,33 @@ def padded_rows(m):
     return 1 << max(0, (m - 1).bit_length())
 
 
+def permuted_signed(A, seed):
+    """The M x n matrix with row i of A, times D_i, at position pi(i) (zeros elsewhere)."""
+    m, n = A.shape
+    M = padded_rows(m)
+    B = np.zeros((M, n), dtype=A.dtype)
+    d = signs(seed, m).astype(A.dtype)
+    for i in range(m):
+        B[scramble(i, M)] = d[i] * A[i]
+    return B
+
+
 def dense_sample(A, idx, seed, s):
-    """sqrt(M/s) (H D [A; 0] / sqrt(M))[idx] from dense matrices (any summation order)."""
+    """sqrt(M/s) (H P D [A; 0] / sqrt(M))[idx] from dense matrices (any summation order)."""
     m, _ = A.shape
     M = padded_rows(m)
-    H = scipy.linalg.hadamard(M)[:, :m] * signs(seed, m)[None, :]
-    return math.sqrt(M / s) * (H[idx] @ A) / math.sqrt(M)
+    H = scipy.linalg.hadamard(M)
+    return math.sqrt(M / s) * (H[idx] @ permuted_signed(A, seed)) / math.sqrt(M)
 
 
-def test_sign_generator_and_padding(orc):
+def test_sign_generator_padding_and_scramble(orc):
     for m in (1, 2, 3, 64, 65, 1000, 4097):
         assert orc.smooth_rows(m) == padded_rows(m)
+    for M in (1, 2, 8, 1024, 8192):
+        pis = [orc.scramble(i, M) for i in range(M)]
+        assert sorted(pis) == list(range(M))  # a permutation
+        assert pis == [scramble(i, M) for i in range(M)]
+    assert orc.scramble(123456, 1 << 24) == scramble(123456, 1 << 24)
     d = signs(12345, 200)
     assert all(orc.rademacher(12345, i) == d[i] for i in range(200))
     big = signs(7, 20000)
@@ -70,8 +99,8 @@ def test_integer_input_matches_the_dense_definition_exactly(orc, m, n, s, seed):
     idx, As = orc.smooth_sample(A, s, seed)
     assert np.array_equal(idx, orc.sample_indices(padded_rows(m), s, seed))
     M = padded_rows(m)
-    H = scipy.linalg.hadamard(M)[:, :m].astype(np.int64) * signs(seed, m).astype(np.int64)[None, :]
-    T = H[idx] @ A.astype(np.int64)  # exact integers
+    H = scipy.linalg.hadamard(M).astype(np.int64)
+    T = H[idx] @ permuted_signed(A, seed).astype(np.int64)  # exact integers
     sc = 1.0 / math.sqrt(s)
     assert np.array_equal(As, T.astype(np.float64) * sc)
     # and the same within rounding as the orthogonal transform written densely
@@ -91,13 +120,15 @@ def test_summation_order_is_the_written_one(orc):
     A = rng.standard_normal((m, n)) * np.exp2(rng.integers(-20, 21, size=(m, n)))
     idx, As = orc.smooth_sample(A, s, seed)
     d = signs(seed, m)
+    M = padded_rows(m)
+    pis = [scramble(i, M) for i in range(m)]
     chunk = 4096
     sc = 1.0 / math.sqrt(s)
     want = np.empty((s, n))
     chain = np.empty((s, n))
     for r in range(s):
         k = int(idx[r])
-        sg = [(-d[i] if bin(k & i).count("1") & 1 else d[i]) for i in range(m)]
+        sg = [(-d[i] if bin(k & pis[i]).count("1") & 1 else d[i]) for i in range(m)]
         for j in range(n):
             T = None
             for c0 in range(0, m, chunk):
@@ -169,3 +200,19 @@ def test_lemma_l31_with_smoothing(orc):
     sv = np.linalg.svd(FQ, compute_uv=False)
     sa = np.linalg.svd(r.A1, compute_uv=False)
     assert np.max(np.abs(sv - 1.0 / sa[::-1]) / sv) < 1e-10
+
+
+def test_smoothed_sketch_of_a_coherent_matrix_is_well_conditioned(orc):
+    """Section 5.1 at n = 300 (m = 6000, kappa = 1e15, c = 3n): kappa(A1) of the
+    smoothed sketch is of the size of a Gaussian sketch's (about 4), and the
+    orthogonality error follows the estimate 4 eps kappa(A1) of Section 5.2."""
+    m, n = 6000, 300
+    A = coherent(m, n, 1e15, 3)
+    for seed in (1, 2):
+        r = orc.rpcholqr(A, 3 * n, seed, nthreads=4, smooth=True)
+        assert r.status == orc.OK
+        sv = np.linalg.svd(r.A1, compute_uv=False)
+        kap = sv[0] / sv[-1]
+        assert kap < 10
+        assert metrics.orth_error(r.Q) < 1e-12
+        assert metrics.orth_error(r.Q) < 20 * 4 * 2.0 ** -52 * kap
