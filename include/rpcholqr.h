@@ -72,6 +72,28 @@ typedef enum {
   RPCHOLQR_BF16X2_REFINE = 2
 } rpcholqr_precision;
 
+/* Option OR'ed into the precision argument of rpcholqr_factor,
+ * rpcholqr_factor_debug, rpcholqr_factor_noalloc and rpcholqr_workspace_bytes:
+ * sample rows of the smoothed matrix F A instead of A's own rows (Algorithm
+ * rpCholesky-QR line 2 with F = F_T D; the remark after Theorem t_prob), for
+ * inputs whose rows are coherent (a few rows carry the column space, such as
+ * the [I; 0] R test matrices of Section 5.1), where sampling A's rows leaves
+ * the sketch rank deficient.  F = F_T D P: A is padded with zero rows to
+ * M = 2^p >= m rows, P moves row i to position pi(i) (x = i * 0x9e3779b97f4a7c15,
+ * x ^= x >> h, x *= 0xbf58476d1ce4e5b9, x ^= x >> h, all mod M, h = max(1, p/2)),
+ * D multiplies it by a random sign (D_i = +1 when bit 63 of SplitMix64 output i
+ * seeded with seed XOR 0x5851f42d4c957f2d is 0), and F_T is the Walsh-Hadamard
+ * transform (F_T(k, q) = (-1)^popcount(k AND q) / sqrt(M)); s row indices are
+ * drawn from [0, M) and A_s = sqrt(M/s) (F [A; 0])(idx, :), formed without
+ * the transform as A_s(r, j) = T(r, j) / sqrt(s) with
+ * T(r, j) = sum_i D_i (-1)^popcount(idx_r AND pi(i)) A(i, j), summed in a fixed
+ * order (chunks of G * 4096 rows, G = max(1, ceil(ceil(m / 4096) / 256)); an
+ * fma chain in ascending i within a chunk; chunks added in ascending order).
+ * Steps 3-8 are unchanged (line 4 uses A itself).  Costs s * m * n extra
+ * multiply-adds and ceil(m / chunk) * s * n doubles of workspace.  Not
+ * available in rpcholqr_precond_factor or the batched entry points. */
+#define RPCHOLQR_SMOOTH 0x100
+
 /* Numerical outcome, written on the device by the library. */
 typedef struct {
   int32_t code;  /* RPCHOLQR_INFO_* */

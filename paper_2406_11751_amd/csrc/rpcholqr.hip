@@ -21,6 +21,7 @@
 #include "small.h"
 #include "wide.h"
 #include "big.h"
+#include "smooth.h"
 #include "batched.h"
 
 namespace {
@@ -149,14 +150,60 @@ bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap =
   return true;
 }
 
-// Workspace bytes for any supported size (0 if unsupported).
-size_t plan_total(int64_t m, int64_t n, int64_t s, int64_t pa_cap, bool refine) {
+// Chunk sums of the smoothed sample (smooth.h): [chunks][n][s] doubles.
+size_t smooth_bytes(int64_t m, int64_t n, int64_t s) {
+  const int64_t chunk = smooth_chunk_rows(m), chunks = (m + chunk - 1) / chunk;
+  return align256((size_t)chunks * (size_t)n * (size_t)s * sizeof(double));
+}
+
+// Workspace bytes for any supported size (0 if unsupported); with smoothing the
+// chunk sums follow the plan's own region.
+size_t plan_total(int64_t m, int64_t n, int64_t s, int64_t pa_cap, bool refine, bool smooth = false) {
+  size_t total = 0;
   if (n > kWideN) {
     BigPlan b;
-    return make_big_plan(m, n, s, &b, pa_cap, refine) ? b.total : 0;
+    if (!make_big_plan(m, n, s, &b, pa_cap, refine)) return 0;
+    total = b.total;
+  } else {
+    Plan p;
+    if (!make_plan(m, n, s, &p, pa_cap, false, refine)) return 0;
+    total = p.total;
   }
-  Plan p;
-  return make_plan(m, n, s, &p, pa_cap, false, refine) ? p.total : 0;
+  return total + (smooth ? smooth_bytes(m, n, s) : 0);
+}
+
+// Line 2: the sample A_s into sa.As (and the optional idx / As copies): the
+// rows of A themselves (F = I), or the rows of the smoothed F [A; 0]
+// (smooth.h) with its chunk sums in smooth_ws.
+bool launch_sample(const SketchArgs& sa, bool smooth, double* smooth_ws, hipStream_t st) {
+  const int64_t m = sa.m, n = sa.n, s = sa.s;
+  if (!smooth) {
+    const int64_t gather_blocks = (s * n + kGatherThreads - 1) / kGatherThreads;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
+    return hipGetLastError() == hipSuccess;
+  }
+  SmoothArgs ma{};
+  ma.m = m;
+  ma.n = (int32_t)n;
+  ma.s = (int32_t)s;
+  ma.seed = sa.seed;
+  ma.M = smooth_padded_rows(m);
+  ma.chunk = smooth_chunk_rows(m);
+  ma.nchunks = (int32_t)((m + ma.chunk - 1) / ma.chunk);
+  ma.scale = 1.0 / std::sqrt((double)s);
+  ma.A = sa.A;
+  ma.lda = sa.lda;
+  ma.partials = smooth_ws;
+  ma.As = sa.As;
+  ma.idx_out = sa.idx_out;
+  ma.As_out = sa.As_out;
+  const int64_t nrb = (s + 15) / 16;
+  const dim3 grid((unsigned)ma.nchunks, (unsigned)((n + 15) / 16),
+                  (unsigned)((nrb + kPassWaves * kSmoothTPW - 1) / (kPassWaves * kSmoothTPW)));
+  hipLaunchKernelGGL(k_smooth_partials, grid, dim3(kSmoothThreads), 0, st, ma);
+  hipLaunchKernelGGL(k_smooth_finish, dim3((unsigned)((s * n + kSmoothThreads - 1) / kSmoothThreads)),
+                     dim3(kSmoothThreads), 0, st, ma);
+  return hipGetLastError() == hipSuccess;
 }
 
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -295,14 +342,15 @@ void with_big_rpt(int rpt, F&& fn) {
 int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda, double* Q,
                    int64_t ldq, double* R, int64_t ldr, int32_t precision, void* ws, size_t ws_bytes,
                    rpcholqr_info* info, void* stream, int64_t* idx, double* As, double* Rs, double* A1, double* G1,
-                   double* R2, const double* Rs_in, int64_t ldrs, int64_t pa_cap, bool timed) {
+                   double* R2, const double* Rs_in, int64_t ldrs, int64_t pa_cap, bool timed, bool smooth) {
   BigPlan p;
   if (!make_big_plan(m, n, s, &p, pa_cap, precision != RPCHOLQR_FP64)) return RPCHOLQR_EUNSUPPORTED;
   const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
   if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
     return RPCHOLQR_EINVAL;
-  if (!ws || ws_bytes < p.total || ((uintptr_t)ws & 255)) return RPCHOLQR_EWORKSPACE;
-  if (overlaps(ws, p.total, A, a_bytes) || overlaps(ws, p.total, Q, q_bytes) || overlaps(ws, p.total, R, r_bytes))
+  const size_t total = p.total + (smooth ? smooth_bytes(m, n, s) : 0);
+  if (!ws || ws_bytes < total || ((uintptr_t)ws & 255)) return RPCHOLQR_EWORKSPACE;
+  if (overlaps(ws, total, A, a_bytes) || overlaps(ws, total, Q, q_bytes) || overlaps(ws, total, R, r_bytes))
     return RPCHOLQR_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
@@ -345,9 +393,7 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     sa.info = inf;
     sa.idx_out = idx;
     sa.As_out = As;
-    const int64_t gather_blocks = (s * n + kGatherThreads - 1) / kGatherThreads;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
-    if (!launched()) return RPCHOLQR_EHIP;
+    if (!launch_sample(sa, smooth, at_ws(p.total), st)) return RPCHOLQR_EHIP;
     BigSketchArgs ba{};
     ba.n = (int32_t)n;
     ba.s = (int32_t)s;
@@ -481,6 +527,9 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
                     size_t ws_bytes, rpcholqr_info* info, void* stream, int64_t* idx, double* As,
                     double* Rs, double* A1, double* G1, double* R2, const double* Rs_in = nullptr,
                     int64_t ldrs = 0, int64_t pa_cap = kPassAMaxBlocks, bool timed = true) {
+  const bool smooth = (precision & RPCHOLQR_SMOOTH) != 0;
+  precision &= ~RPCHOLQR_SMOOTH;
+  if (smooth && Rs_in) return RPCHOLQR_EUNSUPPORTED;
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n) return RPCHOLQR_EINVAL;
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
   if (Rs_in && ldrs < n) return RPCHOLQR_EINVAL;
@@ -489,14 +538,15 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
   if (n > kWideN)
     return factor_big(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, ws, ws_bytes, info, stream, idx, As, Rs,
-                      A1, G1, R2, Rs_in, ldrs, pa_cap, timed);
+                      A1, G1, R2, Rs_in, ldrs, pa_cap, timed, smooth);
   Plan p;
   if (!make_plan(m, n, s, &p, pa_cap, false, refine)) return RPCHOLQR_EUNSUPPORTED;
   const size_t a_bytes = span_bytes(m, n, lda), q_bytes = span_bytes(m, n, ldq), r_bytes = span_bytes(n, n, ldr);
   if (overlaps(A, a_bytes, Q, q_bytes) || overlaps(A, a_bytes, R, r_bytes) || overlaps(Q, q_bytes, R, r_bytes))
     return RPCHOLQR_EINVAL;
-  if (!ws || ws_bytes < p.total || ((uintptr_t)ws & 255)) return RPCHOLQR_EWORKSPACE;
-  if (overlaps(ws, p.total, A, a_bytes) || overlaps(ws, p.total, Q, q_bytes) || overlaps(ws, p.total, R, r_bytes))
+  const size_t total = p.total + (smooth ? smooth_bytes(m, n, s) : 0);
+  if (!ws || ws_bytes < total || ((uintptr_t)ws & 255)) return RPCHOLQR_EWORKSPACE;
+  if (overlaps(ws, total, A, a_bytes) || overlaps(ws, total, Q, q_bytes) || overlaps(ws, total, R, r_bytes))
     return RPCHOLQR_EINVAL;
 
   hipStream_t st = (hipStream_t)stream;
@@ -541,9 +591,7 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
     else
       hipLaunchKernelGGL((k_precond_setup<kSketchMaxN>), dim3(1), dim3(kSketchThreads), 0, st, sa);
   } else {
-    const int64_t gather_blocks = ((int64_t)s * n + kGatherThreads - 1) / kGatherThreads;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)gather_blocks), dim3(kGatherThreads), 0, st, sa);
-    if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
+    if (!launch_sample(sa, smooth, (double*)(base + p.total), st)) return RPCHOLQR_EHIP;
     launch_sketch(p, sa, st);
   }
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
@@ -709,9 +757,9 @@ void* scratch_address() {
 
 // The largest pass-A partial count (a power of two, at most kPassAMaxBlocks)
 // whose workspace fits the scratch array, or 0 if none does.
-int64_t noalloc_pa_cap(int64_t m, int64_t n, int64_t s, bool refine) {
+int64_t noalloc_pa_cap(int64_t m, int64_t n, int64_t s, bool refine, bool smooth) {
   for (int64_t cap = kPassAMaxBlocks; cap >= 1; cap /= 2) {
-    const size_t total = plan_total(m, n, s, cap, refine);
+    const size_t total = plan_total(m, n, s, cap, refine, smooth);
     if (total == 0) return -1;
     if (total <= kScratchBytes) return cap;
   }
@@ -1138,9 +1186,11 @@ extern "C" {
 int32_t rpcholqr_max_n(void) { return kMaxN; }
 
 size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision) {
+  const bool smooth = (precision & RPCHOLQR_SMOOTH) != 0;
+  precision &= ~RPCHOLQR_SMOOTH;
   if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
     return 0;
-  return plan_total(m, n, s, kPassAMaxBlocks, precision != RPCHOLQR_FP64);
+  return plan_total(m, n, s, kPassAMaxBlocks, precision != RPCHOLQR_FP64, smooth);
 }
 
 int32_t rpcholqr_factor(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
@@ -1163,9 +1213,10 @@ int32_t rpcholqr_factor_noalloc(int64_t m, int64_t n, int64_t s, uint64_t seed, 
                                 double* Q, int64_t ldq, double* R, int64_t ldr, int32_t precision,
                                 rpcholqr_info* info, void* stream) {
   if (n < 1 || m < n || s < n || lda < m || ldq < m || ldr < n || !A || !Q || !R || !info) return RPCHOLQR_EINVAL;
-  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
+  const int32_t prec = precision & ~RPCHOLQR_SMOOTH;
+  if (prec != RPCHOLQR_FP64 && prec != RPCHOLQR_FP32_REFINE && prec != RPCHOLQR_BF16X2_REFINE)
     return RPCHOLQR_EUNSUPPORTED;
-  const int64_t cap = noalloc_pa_cap(m, n, s, precision != RPCHOLQR_FP64);
+  const int64_t cap = noalloc_pa_cap(m, n, s, prec != RPCHOLQR_FP64, (precision & RPCHOLQR_SMOOTH) != 0);
   if (cap < 0) return RPCHOLQR_EUNSUPPORTED;
   if (cap == 0) return RPCHOLQR_EWORKSPACE;
   void* ws = scratch_address();

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "lib", "librpcholqr.so")
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "EWORKSPACE", -4: "EUNSUPPORTED"}
 INFO = {0: "OK", 1: "ESKETCH", 2: "ECHOL", 3: "ECHOL2"}
 FP64, FP32_REFINE, BF16X2_REFINE = 0, 1, 2
+SMOOTH = 0x100  # OR into precision: sample rows of the smoothed F A (rpcholqr.h, RPCHOLQR_SMOOTH)
 
 # Every function the header declares, with its ctypes signature.
 _i64, _u64, _i32, _vp, _sz = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t

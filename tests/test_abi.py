@@ -66,6 +66,11 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(1_000_000, 300, 1537) == 0
     assert rq.workspace_bytes(100, 129, 387) == 0       # m < n
     assert rq.workspace_bytes(1_000_000, 513, 1539) == 0
+    # smoothing adds the chunk sums: ceil(m / chunk) * s * n doubles
+    for m, n, s in ((1_000_000, 64, 192), (3000, 300, 900), (20_000_000, 16, 48)):
+        chunk = 4096 * max(1, -(-(-(-m // 4096)) // 256))
+        extra = rq.workspace_bytes(m, n, s, rq.SMOOTH) - rq.workspace_bytes(m, n, s)
+        assert extra >= -(-m // chunk) * s * n * 8, (m, n, s)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

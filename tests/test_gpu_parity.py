@@ -43,12 +43,12 @@ def announce(*args):
     print("case:", *args, flush=True)
 
 
-def check_case(A_h, s, seed, exact_a1=True):
+def check_case(A_h, s, seed, exact_a1=True, smooth=False):
     m, n = A_h.shape
-    announce(f"m={m} n={n} s={s} seed={seed}")
+    announce(f"m={m} n={n} s={s} seed={seed} smooth={smooth}")
     A = dev(A_h)
-    Q, R, info, ex = rq().factor(A, s, seed, debug=True)
-    ref = oracle.rpcholqr(A_h, s, seed, nthreads=NTHREADS)
+    Q, R, info, ex = rq().factor(A, s, seed, debug=True, precision=rq().SMOOTH if smooth else rq().FP64)
+    ref = oracle.rpcholqr(A_h, s, seed, nthreads=NTHREADS, smooth=smooth)
     assert ref.status == oracle.OK
     assert np.array_equal(host(ex["idx"]), ref.idx), "sampled indices differ"
     assert np.array_equal(host(ex["As"]), ref.As), "A_s differs"
@@ -138,6 +138,59 @@ def test_parity_big(m, n, s, kappa, seed):
     _, _, orth, res = check_case(A_h, s, seed)
     assert orth < (1e-12 if s >= 2 * n else 1e-10)
     assert res < 1e-15
+
+
+# Smoothed sampling (F = H D): the sample of the transformed matrix is formed in
+# a fixed order, so idx, A_s, R_s and A1 stay bit-exact; one chunk (m <= 4096),
+# several chunks, chunks of two blocks (m > 4096 * 256), every column class.
+SMOOTH_CASES = [
+    (3000, 24, 72, 1e8, 40),
+    (10000, 64, 192, 1e15, 41),
+    (20001, 100, 300, 1e12, 42),
+    (6000, 200, 600, 1e10, 43),
+    (1_200_000, 16, 48, 1e6, 44),
+    (5000, 5, 1536, 1e4, 45),
+]
+
+
+@pytest.mark.parametrize("m,n,s,kappa,seed", SMOOTH_CASES)
+def test_parity_smoothed(m, n, s, kappa, seed):
+    A_h = gen_usv(m, n, kappa, 100 + seed)
+    _, _, orth, res = check_case(A_h, s, seed, smooth=True)
+    assert orth < 1e-12 and res < 1e-15
+
+
+def coherent(m, n, kappa, seed):
+    """Section 5.1's test matrices A = [I_n; 0] R_A, R_A with geometric singular
+    values and Haar singular vectors (Matlab's randsvd)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U, Ru = np.linalg.qr(rng.standard_normal((n, n)))
+    V, Rv = np.linalg.qr(rng.standard_normal((n, n)))
+    U, V = U * np.sign(np.diag(Ru))[None, :], V * np.sign(np.diag(Rv))[None, :]
+    from workloads import sigma_profile
+
+    A = np.zeros((m, n))
+    A[:n] = (U * sigma_profile(n, kappa)[None, :]) @ V.T
+    return np.asfortranarray(A)
+
+
+@pytest.mark.parametrize("m,n", [(6000, 100), (6000, 300)])
+def test_coherent_matrix_with_and_without_smoothing(m, n):
+    A_h = coherent(m, n, 1e15, 3)
+    announce(f"coherent [I;0] R_A {m}x{n}")
+    # Without smoothing the sample holds few of the n informative rows: the sketch
+    # is rank deficient, which shows as an exactly zero Householder column
+    # (ESKETCH) or, when rounding leaves residue there, as a failed Cholesky
+    # pivot of the then useless preconditioner (ECHOL); the oracle fails alike.
+    ref = oracle.rpcholqr(A_h, 3 * n, 1, nthreads=NTHREADS, keep=False)
+    assert ref.status in (oracle.ESKETCH, oracle.ECHOL)
+    with pytest.raises(rq().RpCholQRError) as e:
+        rq().factor(dev(A_h), 3 * n, 1)
+    assert e.value.code == ref.status
+    if ref.status == oracle.ESKETCH:
+        assert e.value.index == ref.index
+    Qh, Rh, orth, res = check_case(A_h, 3 * n, 1, smooth=True)
+    assert orth < 1e-12 and res < 1e-15
 
 
 @pytest.mark.parametrize("m,n,s,kappa,seed", CASES)
