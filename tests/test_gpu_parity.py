@@ -422,3 +422,14 @@ def test_parity_full_size_1e6x64(kappa):
     Qh, Rh, orth, res = check_case(A_h, s, 0)
     print(f"  kappa={kappa:.0e}: orth={orth:.3e} residual={res:.3e}", flush=True)
     assert orth <= 1e-12 and res <= 1e-15
+
+
+@pytest.mark.parametrize("kappa", [1e8, 1e15])
+def test_parity_full_size_1e6x128(kappa):
+    # The 128-column class at 1,000,000 rows (s = 3n = 384): bit-exact idx, A_s,
+    # R_s and A1 across the half boundary of the row solve on every row.
+    m, n, s = 1_000_000, 128, 384
+    A_h = gen_usv(m, n, kappa, 0)
+    Qh, Rh, orth, res = check_case(A_h, s, 0)
+    print(f"  kappa={kappa:.0e}: orth={orth:.3e} residual={res:.3e}", flush=True)
+    assert orth <= 1e-12 and res <= 1e-15
