@@ -109,9 +109,11 @@ typedef struct {
 /* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
 #define RPCHOLQR_INFO_ECHOL2 3
 
-/* Largest n the library accepts (512).  Supported sizes: s <= 1536 and
- * n <= 512 for RPCHOLQR_FP64, n <= 64 for the refined precisions, n <= 128 in
- * the batched entry points; other sizes give RPCHOLQR_EUNSUPPORTED. */
+/* Largest n the library accepts (512).  Supported sizes: n <= 512 for
+ * RPCHOLQR_FP64 with s <= 1536, and s <= 8192 when n > 128 (the sketch then
+ * streams the sample from the workspace); n <= 64 for the refined precisions;
+ * n <= 128 and s <= 1536 in the batched entry points; other sizes give
+ * RPCHOLQR_EUNSUPPORTED. */
 int32_t rpcholqr_max_n(void);
 
 /* Device workspace in bytes needed by rpcholqr_factor / rpcholqr_factor_debug
@@ -228,7 +230,7 @@ int32_t rpcholqr_timing_read(double* ms, int32_t count);
  *   batch          number of problems (>= 1)
  *   m, n, s, seed, lda, ldq, ldr
  *                  HOST arrays of length batch, per problem as in
- *                  rpcholqr_factor (1 <= n <= rpcholqr_max_n(), s <= 1536)
+ *                  rpcholqr_factor (1 <= n <= 128, s <= 1536)
  *   A, Q, R        HOST arrays of length batch holding DEVICE pointers; within
  *                  a problem Q must not overlap A, R must not overlap A or Q;
  *                  different problems must not share Q or R memory

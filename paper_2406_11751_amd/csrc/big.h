@@ -222,6 +222,175 @@ __global__ __launch_bounds__(kTrailThreads) void k_sketch_trail(BigSketchArgs a)
   }
 }
 
+// Streaming sketch for samples beyond 96 rows per lane (s > 1536): the same
+// steps with the same arithmetic, but the sample columns stay in the sample
+// buffer (global memory, updated in place) and every pass over a column streams
+// it, 16 rows per load, lane l16 taking rows l16, l16 + 16, ... in order.  The
+// reflector is staged in LDS.  Panels are kGmPW columns wide.
+constexpr int kGmPW = 16;
+constexpr int kGmThreads = 16 * kGmPW;
+constexpr int kGmMaxRows = 8192;            // LDS: two staged reflectors
+constexpr int kGmUnroll = 16;               // rows per lane and chunk of a streamed pass
+
+// The lane's rows r = l16 + 16 t, t < T, are streamed in chunks of kGmUnroll,
+// the next chunk's loads issued before the current chunk is used.  Rows at or
+// past s read as zero.
+template <typename F>
+__device__ __forceinline__ void gm_stream(const double* x, int l16, int T, int s, F&& body) {
+  double cur[kGmUnroll], nxt[kGmUnroll];
+  auto load = [&](int t0, double (&dst)[kGmUnroll]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kGmUnroll; ++u) {
+      const int r = l16 + 16 * (t0 + u);
+      dst[u] = (t0 + u < T && r < s) ? x[r] : 0.0;
+    }
+  };
+  load(0, cur);
+  for (int t0 = 0; t0 < T; t0 += kGmUnroll) {
+    load(t0 + kGmUnroll, nxt);
+#pragma unroll
+    for (int u = 0; u < kGmUnroll; ++u) body(t0 + u, cur[u]);
+#pragma unroll
+    for (int u = 0; u < kGmUnroll; ++u) cur[u] = nxt[u];
+  }
+}
+
+// fma chain of v(r) * x(r) over the lane's rows in ascending order (v zero at
+// and past s).
+__device__ __forceinline__ double gm_dot(const double* __restrict__ v, const double* x, int l16, int T, int s) {
+  double p = 0.0;
+  gm_stream(x, l16, T, s, [&](int t, double xv) __attribute__((always_inline)) {
+    if (t < T) p = __builtin_fma(v[l16 + 16 * t], xv, p);
+  });
+  return p;
+}
+
+// x(r) = fma(-tt, v(r), x(r)) over the lane's rows below s; the new values of
+// rows r0 and r1 are returned in k0 / k1 by the lanes holding them.
+__device__ __forceinline__ void gm_update(const double* __restrict__ v, double* x, double tt, int l16, int T, int s,
+                                          int r0, int r1, double& k0, double& k1) {
+  gm_stream(x, l16, T, s, [&](int t, double xv) __attribute__((always_inline)) {
+    const int r = l16 + 16 * t;
+    if (t < T && r < s) {
+      const double w = __builtin_fma(-tt, v[r], xv);
+      x[r] = w;
+      if (r == r0) k0 = w;
+      if (r == r1) k1 = w;
+    }
+  });
+}
+
+__global__ __launch_bounds__(kGmThreads) void k_sketch_panel_gm(BigSketchArgs a) {
+  __shared__ double vbuf[2][kGmMaxRows];
+  __shared__ double tau_s[2];
+  __shared__ int bad[2];
+  const int n = a.n, s = a.s, c0 = a.c0;
+  if (c0 > 0 && a.info[0] != 0) return;  // an earlier panel failed
+  if (c0 == 0 && threadIdx.x == 0) {
+    a.info[0] = 0;
+    a.info[1] = -1;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int j = c0 + 4 * wave + q;  // my column
+  const int kend = min(c0 + kGmPW, n);
+  const int T = (s + 15) / 16;
+  double* col = a.As + (int64_t)(j < n ? j : 0) * s;
+  for (int e = threadIdx.x; e < 2 * kGmMaxRows; e += kGmThreads) (&vbuf[0][0])[e] = 0.0;
+  if (threadIdx.x < 2) bad[threadIdx.x] = -1;
+  // alpha: row k of the owner column after its last update, kept by the lane
+  // holding it (for the first panel column, read below)
+  double diag = 0.0;
+  __syncthreads();
+
+  // Reflector k from my column (k == j), run by my 16-lane group.
+  auto reflector = [&](int k) __attribute__((always_inline)) {
+    const int buf = k & 1;
+    double p = 0.0;
+    gm_stream(col, l16, T, s, [&](int t, double xv) __attribute__((always_inline)) {
+      const double x = (l16 + 16 * t >= k) ? xv : 0.0;
+      if (t < T) p = __builtin_fma(x, x, p);
+    });
+    const int owner_lane = 16 * q + (k & 15);
+    const double nu2 = readlane_d(row16_sum(p), owner_lane);
+    const double alpha = readlane_d(diag, owner_lane);
+    if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
+      if (l16 == 0) bad[buf] = k;
+      return;
+    }
+    const double nu = __builtin_sqrt(nu2);
+    const double beta = (alpha >= 0.0) ? -nu : nu;
+    const double d = 1.0 / (alpha - beta);
+    const double tau = (beta - alpha) / beta;
+    gm_stream(col, l16, T, s, [&](int t, double xv) __attribute__((always_inline)) {
+      const int r = l16 + 16 * t;
+      if (t < T && r < s) vbuf[buf][r] = (r >= k) ? ((r == k) ? 1.0 : xv * d) : 0.0;
+    });
+    if (l16 == 0) {
+      tau_s[buf] = tau;
+      a.tau[k] = tau;
+      a.Rg[(int64_t)k * n + k] = beta;
+    }
+  };
+
+  if (j == c0) {
+    diag = col[c0];  // row c0 of column c0 (c0 < n <= s)
+    reflector(c0);
+  }
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    if (bad[k & 1] >= 0) break;
+    const int buf = k & 1;
+    // Reflector k replaces sample column k, where the trailing-column kernel reads it.
+    for (int r = threadIdx.x; r < s; r += kGmThreads) a.As[r + (int64_t)k * s] = vbuf[buf][r];
+    if (j > k && j < kend) {
+      const double tt = tau_s[buf] * row16_sum(gm_dot(vbuf[buf], col, l16, T, s));
+      double w = 0.0;
+      gm_update(vbuf[buf], col, tt, l16, T, s, k, k + 1, w, diag);
+      if (l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = w;
+      if (j == k + 1) reflector(k + 1);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int b = bad[0] >= 0 ? bad[0] : bad[1];
+    if (b >= 0) {
+      a.info[0] = 1;  // ESKETCH
+      a.info[1] = b;
+    }
+  }
+}
+
+// Reflectors c0 .. kend-1 applied to the columns after the panel, one 16-lane
+// group per column, the reflector staged in LDS (double buffered).
+__global__ __launch_bounds__(kGmThreads) void k_sketch_trail_gm(BigSketchArgs a) {
+  __shared__ double vbuf[2][kGmMaxRows];
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int n = a.n, s = a.s, c0 = a.c0;
+  const int kend = min(c0 + a.pw, n);
+  const int j = kend + kGmPW * (int)blockIdx.x + 4 * wave + q;
+  const int T = (s + 15) / 16;
+  double* col = a.As + (int64_t)(j < n ? j : 0) * s;
+  auto stage = [&](int k, int buf) __attribute__((always_inline)) {
+    for (int e = threadIdx.x; e < 16 * T; e += kGmThreads) vbuf[buf][e] = (e < s) ? a.As[e + (int64_t)k * s] : 0.0;
+  };
+  stage(c0, 0);
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    const int buf = (k - c0) & 1;
+    if (k + 1 < kend) stage(k + 1, buf ^ 1);  // buffer buf ^ 1 was last read in step k - 1
+    if (j < n) {
+      const double tt = a.tau[k] * row16_sum(gm_dot(vbuf[buf], col, l16, T, s));
+      double w = 0.0, unused = 0.0;
+      gm_update(vbuf[buf], col, tt, l16, T, s, k, -1, w, unused);
+      if (l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = w;
+    }
+    __syncthreads();
+  }
+}
+
 struct BigFinishArgs {
   int32_t n, nmax;
   const double* Rg;        // element (k, j) at Rg[k * rs_k + j * rs_j]

@@ -30,7 +30,6 @@ using namespace rpq;
 
 constexpr int kMaxN = kBigMaxN;
 constexpr int kWideN = 128;  // column class of 64 < n <= 128 (two-half row solve, separate Gram pass)
-constexpr int kBigMaxSketchRows = 16 * 96;  // panel sketch: up to 96 sample rows per lane
 constexpr int kMaxSketchRows = 1536;  // generic sketch kernel keeps 2*s doubles in LDS
 constexpr int kPassAMaxBlocks = 512;
 static_assert(kPassAMaxBlocks <= kReduceChunk * kMaxPartial2, "second-level partial count");
@@ -113,13 +112,13 @@ struct BigPlan {
 bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap = kPassAMaxBlocks,
                    bool refine = false) {
   if (n <= kWideN || n > kBigMaxN || m < n || s < n || refine) return false;
-  if (s > kBigMaxSketchRows) return false;
+  if (s > kGmMaxRows) return false;  // s > 16 * 96: the streaming panel sketch
   p->nmax = (int)((n + kBigBlock - 1) / kBigBlock) * kBigBlock;
   p->NB = p->nmax / 16;
   p->NP = p->nmax / kWH;
   p->E = (int64_t)p->NB * (p->NB + 1) / 2 * 256;
   const int64_t rows = (s + 15) / 16;
-  p->rpt = rows <= 16 ? 16 : rows <= 24 ? 24 : rows <= 32 ? 32 : rows <= 48 ? 48 : rows <= 64 ? 64 : 96;
+  p->rpt = rows <= 16 ? 16 : rows <= 24 ? 24 : rows <= 32 ? 32 : rows <= 48 ? 48 : rows <= 64 ? 64 : rows <= 96 ? 96 : 0;
   const int ng = p->nmax / kBigBlock;
   p->ngroups = ng * (ng + 1) / 2;
   const int64_t rblocks = (m + kGRows - 1) / kGRows;
@@ -401,19 +400,31 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     ba.tau = at_ws(p.off_tau);
     ba.Rg = at_ws(p.off_Rg);
     ba.info = inf;
-    with_big_rpt(p.rpt, [&](auto rp) {
-      constexpr int RPT = decltype(rp)::value;
-      constexpr int PW = panel_width<RPT>();
-      ba.pw = PW;
-      for (int c0 = 0; c0 < n; c0 += PW) {
+    if (p.rpt == 0) {
+      ba.pw = kGmPW;
+      for (int c0 = 0; c0 < n; c0 += kGmPW) {
         ba.c0 = c0;
-        hipLaunchKernelGGL((k_sketch_panel<RPT>), dim3(1), dim3(16 * PW), 0, st, ba);
-        const int64_t trail = n - std::min<int64_t>(c0 + PW, n);
+        hipLaunchKernelGGL(k_sketch_panel_gm, dim3(1), dim3(kGmThreads), 0, st, ba);
+        const int64_t trail = n - std::min<int64_t>(c0 + kGmPW, n);
         if (trail > 0)
-          hipLaunchKernelGGL((k_sketch_trail<RPT>), dim3((unsigned)((trail + 15) / 16)), dim3(kTrailThreads), 0, st,
-                             ba);
+          hipLaunchKernelGGL(k_sketch_trail_gm, dim3((unsigned)((trail + kGmPW - 1) / kGmPW)), dim3(kGmThreads), 0,
+                             st, ba);
       }
-    });
+    } else {
+      with_big_rpt(p.rpt, [&](auto rp) {
+        constexpr int RPT = decltype(rp)::value;
+        constexpr int PW = panel_width<RPT>();
+        ba.pw = PW;
+        for (int c0 = 0; c0 < n; c0 += PW) {
+          ba.c0 = c0;
+          hipLaunchKernelGGL((k_sketch_panel<RPT>), dim3(1), dim3(16 * PW), 0, st, ba);
+          const int64_t trail = n - std::min<int64_t>(c0 + PW, n);
+          if (trail > 0)
+            hipLaunchKernelGGL((k_sketch_trail<RPT>), dim3((unsigned)((trail + 15) / 16)), dim3(kTrailThreads), 0,
+                               st, ba);
+        }
+      });
+    }
     fa.Rg = at_ws(p.off_Rg);
     fa.rs_k = n;
     fa.rs_j = 1;

@@ -59,11 +59,15 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100_000, 65, 1537) == 0
     assert rq.workspace_bytes(100_000, 100, 300, precision=rq.FP32_REFINE) == 0
     assert rq.workspace_bytes(100_000, 64, 192, precision=rq.FP32_REFINE) > 0
-    # 128 < n <= 512: the panel sketch takes s <= 1536; columns padded to 128k
+    # 128 < n <= 512: the register panel sketch takes s <= 1536, the streaming
+    # one s <= 8192; columns padded to 128k
     for n in (129, 256, 300, 512):
         assert rq.workspace_bytes(1_000_000, n, 3 * n) >= 3 * n * n * 8
     assert rq.workspace_bytes(1_000_000, 512, 1536) > rq.workspace_bytes(1_000_000, 256, 768)
-    assert rq.workspace_bytes(1_000_000, 300, 1537) == 0
+    assert rq.workspace_bytes(1_000_000, 300, 1537) >= 1537 * 300 * 8
+    assert rq.workspace_bytes(16_000_000, 512, 5120) >= 5120 * 512 * 8
+    assert rq.workspace_bytes(1_000_000, 300, 8192) > 0
+    assert rq.workspace_bytes(1_000_000, 300, 8193) == 0
     assert rq.workspace_bytes(100, 129, 387) == 0       # m < n
     assert rq.workspace_bytes(1_000_000, 513, 1539) == 0
     # smoothing adds the chunk sums: ceil(m / chunk) * s * n doubles

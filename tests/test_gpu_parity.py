@@ -117,7 +117,8 @@ WIDE_CASES = [
 # earlier panels of A1 read back), the 128 x 128 Gram groups, the Cholesky with
 # G in global memory and the MFMA pass B.  Ragged n (129, 200, 300), every
 # padded width (256, 384, 512), every sketch rows-per-lane class (32 .. 96),
-# the largest s, a single row-panel group, s = 2n.
+# the largest s of the register sketch, a single row-panel group, s = 2n; and
+# s = 1537 .. 8192 through the streaming sketch.
 BIG_CASES = [
     (3000, 129, 387, 1e8, 30),
     (20001, 200, 600, 1e12, 31),
@@ -129,6 +130,11 @@ BIG_CASES = [
     (1000, 140, 1536, 1e3, 37),     # largest s, few rows
     (230, 130, 390, 1e4, 38),       # a single row-panel group
     (3001, 160, 260, 1e9, 39),      # s in 257..384 (24 rows per lane)
+    # s > 1536: the streaming panel sketch (sample columns in the workspace)
+    (20000, 150, 1537, 1e8, 50),    # one row past the register sketch
+    (30000, 300, 3000, 1e12, 51),   # s = 10n
+    (12000, 512, 5120, 1e10, 52),   # s = 10n at the largest n
+    (9000, 130, 8192, 1e4, 53),     # largest s, ragged n
 ]
 
 
