@@ -392,11 +392,12 @@ def main():
                    one_thread=dict(value=bytes_alg / dt1 / 1e9, unit="GB/s", cores=1,
                                    seconds_per_factorization=dt1, factorizations_per_s=1.0 / dt1))
 
-    # Refined precisions on the same input: lower-precision Gram in pass 1, FP64
-    # Cholesky-QR second pass.
+    # Mixed precisions on the same input: the refined ones (lower-precision Gram
+    # in pass 1, FP64 Cholesky-QR second pass) and A1 kept in binary32 between
+    # the passes.
     ws_r = torch.empty(rq.workspace_bytes(m, n, s, rq.FP32_REFINE), dtype=torch.uint8, device=dev)
     mixed = None if args.no_mixed else {}
-    for pname in () if args.no_mixed else ("FP32_REFINE", "BF16X2_REFINE"):
+    for pname in () if args.no_mixed else ("A1_FP32", "FP32_REFINE", "BF16X2_REFINE"):
         prec = getattr(rq, pname)
 
         def step_refine():

@@ -65,11 +65,22 @@ typedef enum {
  *   RPCHOLQR_BF16X2_REFINE as RPCHOLQR_FP32_REFINE, but step 5 splits each
  *       float-rounded entry of A1 into bfloat16 hi + lo and forms
  *       hi^T hi + hi^T lo + lo^T hi with float accumulation (about 16
- *       significant bits); the second pass is the same binary64 pass. */
+ *       significant bits); the second pass is the same binary64 pass.
+ *   RPCHOLQR_A1_FP32       not in the paper: the preconditioned matrix
+ *       A1 = A R_s^{-1} (step 4, computed in binary64 exactly as with
+ *       RPCHOLQR_FP64) is rounded to binary32 where it is kept between the two
+ *       passes, halving that traffic; the Gram matrix (step 5) and Q = A1 R2^{-1}
+ *       (step 7) are formed in binary64 from the stored binary32 values, so Q is
+ *       as orthogonal as with RPCHOLQR_FP64, while ||A - Q R|| / ||A|| grows to
+ *       about u32 kappa(A1) (the rounding of A1 enters the residual only; Theorem
+ *       t_perturb2).  n <= 64.  The float copy of A1 lives in the Q buffer
+ *       itself: row r of column j, 64 b <= r < 64 b + 64, at byte offset
+ *       8 (64 b + j ldq) + 4 (r - 64 b), inside the memory of the same rows of Q. */
 typedef enum {
   RPCHOLQR_FP64 = 0,
   RPCHOLQR_FP32_REFINE = 1,
-  RPCHOLQR_BF16X2_REFINE = 2
+  RPCHOLQR_BF16X2_REFINE = 2,
+  RPCHOLQR_A1_FP32 = 3
 } rpcholqr_precision;
 
 /* Option OR'ed into the precision argument of rpcholqr_factor,
@@ -111,7 +122,8 @@ typedef struct {
 
 /* Largest n the library accepts (512).  Supported sizes: n <= 512 for
  * RPCHOLQR_FP64 with s <= 1536, and s <= 8192 when n > 128 (the sketch then
- * streams the sample from the workspace); n <= 64 for the refined precisions;
+ * streams the sample from the workspace); n <= 64 for the refined precisions
+ * and RPCHOLQR_A1_FP32;
  * n <= 128 and s <= 1536 in the batched entry points; other sizes give
  * RPCHOLQR_EUNSUPPORTED. */
 int32_t rpcholqr_max_n(void);

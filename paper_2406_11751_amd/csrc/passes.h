@@ -50,6 +50,15 @@ __device__ __forceinline__ void load_row(double (&t)[NMAX], const double* __rest
   for (int j = 0; j < NMAX; ++j) t[j] = (valid && j < n) ? (base + (int64_t)j * lda)[lane] : 0.0;
 }
 
+// The binary32 copy of A1 (RPCHOLQR_A1_FP32) inside the Q buffer: rows
+// 64b .. 64b+63 of column j occupy the first 256 bytes (two full 128-byte
+// lines) of the same rows of Q, so a 64-row block of Q overwrites only its own
+// rows' copy.
+constexpr int kA1fRows = 64;
+__device__ __forceinline__ float* a1f_ptr(double* Q, int64_t ldq, int64_t r, int64_t j) {
+  return reinterpret_cast<float*>(Q + (r & ~(int64_t)(kA1fRows - 1)) + j * ldq) + (r & (kA1fRows - 1));
+}
+
 struct PassAArgs {
   int64_t m;
   int32_t n;
@@ -73,17 +82,25 @@ __device__ __forceinline__ void sum_waves_to_partial(const double* red, double* 
   }
 }
 
-template <int NMAX>
+template <int NMAX, bool F32A1 = false>
 __device__ __forceinline__ void store_a1(const PassAArgs& a, const double (&t)[NMAX], int64_t r0, int lane,
                                          bool valid) {
   int n = a.n;
   int64_t ldw = a.ldw;
   asm volatile("" : "+s"(n), "+s"(ldw));
-  double* base = a.W + r0;
   if (valid) {
+    if constexpr (F32A1) {
+      // r0 is a multiple of 64: the wave's rows are one block of the copy
+      float* base = reinterpret_cast<float*>(a.W + r0) + lane;
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j)
-      if (j < n) (base + (int64_t)j * ldw)[lane] = t[j];
+      for (int j = 0; j < NMAX; ++j)
+        if (j < n) base[2 * (int64_t)j * ldw] = (float)t[j];
+    } else {
+      double* base = a.W + r0;
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < n) (base + (int64_t)j * ldw)[lane] = t[j];
+    }
   }
 }
 
@@ -109,8 +126,11 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 constexpr int kGramF64 = 0, kGramF32 = 1, kGramBF16x2 = 2;
 
-template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
+// F32A1: A1 is rounded to binary32, stored as such (a1f_ptr), and the Gram is
+// formed from the rounded values.
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64, bool F32A1 = false>
 __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk) {
+  static_assert(!F32A1 || (MODE == kSolveGram && GP == kGramF64), "binary32 A1 with the FP64 Gram");
   static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA Gram tiles");
   constexpr int NB = GramShape<NMAX>::NB, NT = GramShape<NMAX>::NT, E = GramShape<NMAX>::E;
   constexpr int LDX = NMAX + 1;
@@ -142,7 +162,11 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) t[j] = 0.0;
       }
-      store_a1<NMAX>(a, t, r0, lane, valid);
+      if constexpr (F32A1) {
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) t[j] = (double)(float)t[j];
+      }
+      store_a1<NMAX, F32A1>(a, t, r0, lane, valid);
     }
     if constexpr (MODE == kSolveOnly) continue;
 #pragma unroll
@@ -245,9 +269,9 @@ __device__ __forceinline__ void passA_body(const PassAArgs& a, int bid, int nblk
   sum_waves_to_partial<E>(lds, a.partials, bid);
 }
 
-template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64, bool F32A1 = false>
 __global__ __launch_bounds__(kPassThreads, 2) void k_passA_mfma(PassAArgs a) {
-  passA_body<NMAX, MODE, GP>(a, blockIdx.x, gridDim.x);
+  passA_body<NMAX, MODE, GP, F32A1>(a, blockIdx.x, gridDim.x);
 }
 
 struct PassBArgs {
@@ -324,9 +348,86 @@ __device__ __forceinline__ void passB_body(const PassBArgs& a, int bid, int nblk
   }
 }
 
+// pass B reading the binary32 copy of A1 (a1f_ptr), widened exactly: as
+// passB_body, but a wave takes a whole 64-row block of the copy (four 16-row
+// blocks) and loads all of it before storing any of its rows of Q.
 template <int NMAX>
+__device__ __forceinline__ void passB_f32_body(const PassBArgs& a, int bid, int nblk) {
+  static_assert(NMAX % 16 == 0 && NMAX <= 64, "MFMA tiles");
+  constexpr int NB = NMAX / 16, NKC = NMAX / 4, SB = kA1fRows / 16;
+  constexpr int NOPS = NKC * NB - 2 * NB * (NB - 1);
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  double t2[NOPS];
+  {
+    int o = 0;
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int cb = kc / 4; cb < NB; ++cb) t2[o++] = a.T2[(4 * kc + g4) * NMAX + 16 * cb + i16];
+  }
+  const int64_t blocks = (a.m + kA1fRows - 1) / kA1fRows;
+  const int64_t nw = (int64_t)nblk * (kPassBThreads / kWave);
+  for (int64_t it = (int64_t)bid * (kPassBThreads / kWave) + wave; it < blocks; it += nw) {
+    const int64_t r0 = (blocks - 1 - it) * kA1fRows;  // last blocks first, as in passB_body
+    const float* src = reinterpret_cast<const float*>(a.Q + r0);
+    float x[SB][NKC];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) {
+        const int col = 4 * kc + g4;
+        const int64_t row = r0 + 16 * sb + i16;
+        x[sb][kc] = (row < a.m && col < a.n) ? src[2 * (int64_t)col * a.ldq + 16 * sb + i16] : 0.0f;
+      }
+    // Every load of the block has returned before the first store of the
+    // block is issued (the stores overwrite the copy they read).
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) asm volatile("" : "+v"(x[sb][kc])::"memory");
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t row = r0 + 16 * sb + i16;
+      d4 acc[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+      int o = 0;
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+        for (int cb = kc / 4; cb < NB; ++cb) {
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(t2[o], (double)x[sb][kc], acc[cb], 0, 0, 0);
+          ++o;
+        }
+      if (row < a.m) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * cb + g4 + 4 * v;
+            if (col < a.n) a.Q[row + (int64_t)col * a.ldq] = acc[cb][v];
+          }
+      }
+    }
+  }
+}
+
+template <int NMAX, bool F32A1 = false>
 __global__ __launch_bounds__(kPassBThreads) void k_passB(PassBArgs a) {
-  passB_body<NMAX>(a, blockIdx.x, gridDim.x);
+  if constexpr (F32A1)
+    passB_f32_body<NMAX>(a, blockIdx.x, gridDim.x);
+  else
+    passB_body<NMAX>(a, blockIdx.x, gridDim.x);
+}
+
+// The binary32 copy of A1 widened into a caller's m x n column-major buffer
+// (debug output).
+__global__ void k_export_a1f(const double* Q, int64_t ldq, int64_t m, int32_t n, double* out, int64_t ldo) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r < m && j < n) out[r + j * ldo] = (double)*a1f_ptr(const_cast<double*>(Q), ldq, r, j);
 }
 
 }  // namespace rpq

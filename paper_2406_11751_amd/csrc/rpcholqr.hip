@@ -171,6 +171,16 @@ size_t plan_total(int64_t m, int64_t n, int64_t s, int64_t pa_cap, bool refine, 
   return total + (smooth ? smooth_bytes(m, n, s) : 0);
 }
 
+bool is_refine(int32_t prec) { return prec == RPCHOLQR_FP32_REFINE || prec == RPCHOLQR_BF16X2_REFINE; }
+
+// Workspace bytes for a precision value (RPCHOLQR_SMOOTH masked off); 0 when
+// the combination is not supported.
+size_t precision_total(int64_t m, int64_t n, int64_t s, int64_t pa_cap, int32_t prec, bool smooth) {
+  if (prec != RPCHOLQR_FP64 && !is_refine(prec) && prec != RPCHOLQR_A1_FP32) return 0;
+  if (prec == RPCHOLQR_A1_FP32 && n > kSketchMaxN) return 0;
+  return plan_total(m, n, s, pa_cap, is_refine(prec), smooth);
+}
+
 // Line 2: the sample A_s into sa.As (and the optional idx / As copies): the
 // rows of A themselves (F = I), or the rows of the smoothed F [A; 0]
 // (smooth.h) with its chunk sums in smooth_ws.
@@ -257,15 +267,15 @@ int device_cus() {
 
 // Pass A launch.  Returns the number of workgroups launched (= Gram partials
 // written).
-template <int NMAX, int MODE = kSolveGram, int GP = kGramF64>
+template <int NMAX, int MODE = kSolveGram, int GP = kGramF64, bool F32A1 = false>
 int launch_passes_A(const Plan& p, const PassAArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_passA_mfma<NMAX, MODE, GP>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
+  hipLaunchKernelGGL((k_passA_mfma<NMAX, MODE, GP, F32A1>), dim3(p.PA), dim3(kPassThreads), 0, st, a);
   return p.PA;
 }
 
-template <int NMAX>
+template <int NMAX, bool F32A1 = false>
 void launch_pass_B(const Plan& p, const PassBArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_passB<NMAX>), dim3(p.PB), dim3(kPassBThreads), 0, st, a);
+  hipLaunchKernelGGL((k_passB<NMAX, F32A1>), dim3(p.PB), dim3(kPassBThreads), 0, st, a);
 }
 
 // Pass A for 64 < n <= 128: the two-half row solve, then the Gram pass.
@@ -545,8 +555,10 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
   if (!A || !Q || !R || !info) return RPCHOLQR_EINVAL;
   if (Rs_in && ldrs < n) return RPCHOLQR_EINVAL;
   if (s > INT32_MAX) return RPCHOLQR_EUNSUPPORTED;
-  const bool refine = precision == RPCHOLQR_FP32_REFINE || precision == RPCHOLQR_BF16X2_REFINE;
-  if (precision != RPCHOLQR_FP64 && !refine) return RPCHOLQR_EUNSUPPORTED;
+  const bool refine = is_refine(precision);
+  const bool a1f = precision == RPCHOLQR_A1_FP32;
+  if (precision != RPCHOLQR_FP64 && !refine && !a1f) return RPCHOLQR_EUNSUPPORTED;
+  if (a1f && (n > kSketchMaxN || Rs_in)) return RPCHOLQR_EUNSUPPORTED;
   if (n > kWideN)
     return factor_big(m, n, s, seed, A, lda, Q, ldq, R, ldr, precision, ws, ws_bytes, info, stream, idx, As, Rs,
                       A1, G1, R2, Rs_in, ldrs, pa_cap, timed, smooth);
@@ -628,15 +640,21 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
       pa_grid = launch_passes_A<NM, kSolveGram, kGramF32>(p, pa, st);
     else if (precision == RPCHOLQR_BF16X2_REFINE)
       pa_grid = launch_passes_A<NM, kSolveGram, kGramBF16x2>(p, pa, st);
+    else if (a1f)
+      pa_grid = launch_passes_A<NM, kSolveGram, kGramF64, true>(p, pa, st);
     else
       pa_grid = launch_passes_A<NM>(p, pa, st);
   });
   if (hipGetLastError() != hipSuccess) return RPCHOLQR_EHIP;
   const int g2 = (pa_grid + kReduceChunk - 1) / kReduceChunk;  // <= p.G2
   mark();
-  if (A1 && hipMemcpy2DAsync(A1, (size_t)m * sizeof(double), Q, (size_t)ldq * sizeof(double),
-                             (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (A1 && a1f) {
+    hipLaunchKernelGGL(k_export_a1f, dim3((unsigned)((m + 255) / 256), (unsigned)n), dim3(256), 0, st,
+                       (const double*)Q, ldq, m, (int32_t)n, A1, m);
+  } else if (A1 && hipMemcpy2DAsync(A1, (size_t)m * sizeof(double), Q, (size_t)ldq * sizeof(double),
+                                    (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess) {
     return RPCHOLQR_EHIP;
+  }
 
   hipLaunchKernelGGL(k_reduce_partials, dim3((p.E + kReduceThreads - 1) / kReduceThreads, g2),
                      dim3(kReduceThreads), 0, st, (const double*)part, pa_grid, p.E, part2, (const int32_t*)inf);
@@ -692,7 +710,12 @@ int32_t factor_impl(int64_t m, int64_t n, int64_t s, uint64_t seed, const double
     if (p.nmax == kWideN)
       launch_pass_B_wide(m, pb, st);
     else
-      with_nmax(p.nmax, [&](auto nm) { launch_pass_B<decltype(nm)::value>(p, pb, st); });
+      with_nmax(p.nmax, [&](auto nm) {
+        if (a1f)
+          launch_pass_B<decltype(nm)::value, true>(p, pb, st);
+        else
+          launch_pass_B<decltype(nm)::value>(p, pb, st);
+      });
   };
   if (substitute) {
     hipLaunchKernelGGL(k_solve_operands, dim3(1), dim3(kCholThreads), 0, st, (const double*)R2s, (int)n, p.nmax, tri3,
@@ -1199,9 +1222,7 @@ int32_t rpcholqr_max_n(void) { return kMaxN; }
 size_t rpcholqr_workspace_bytes(int64_t m, int64_t n, int64_t s, int32_t precision) {
   const bool smooth = (precision & RPCHOLQR_SMOOTH) != 0;
   precision &= ~RPCHOLQR_SMOOTH;
-  if (precision != RPCHOLQR_FP64 && precision != RPCHOLQR_FP32_REFINE && precision != RPCHOLQR_BF16X2_REFINE)
-    return 0;
-  return plan_total(m, n, s, kPassAMaxBlocks, precision != RPCHOLQR_FP64, smooth);
+  return precision_total(m, n, s, kPassAMaxBlocks, precision, smooth);
 }
 
 int32_t rpcholqr_factor(int64_t m, int64_t n, int64_t s, uint64_t seed, const double* A, int64_t lda,
@@ -1227,7 +1248,7 @@ int32_t rpcholqr_factor_noalloc(int64_t m, int64_t n, int64_t s, uint64_t seed, 
   const int32_t prec = precision & ~RPCHOLQR_SMOOTH;
   if (prec != RPCHOLQR_FP64 && prec != RPCHOLQR_FP32_REFINE && prec != RPCHOLQR_BF16X2_REFINE)
     return RPCHOLQR_EUNSUPPORTED;
-  const int64_t cap = noalloc_pa_cap(m, n, s, prec != RPCHOLQR_FP64, (precision & RPCHOLQR_SMOOTH) != 0);
+  const int64_t cap = noalloc_pa_cap(m, n, s, is_refine(prec), (precision & RPCHOLQR_SMOOTH) != 0);
   if (cap < 0) return RPCHOLQR_EUNSUPPORTED;
   if (cap == 0) return RPCHOLQR_EWORKSPACE;
   void* ws = scratch_address();

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "lib", "librpcholqr.so")
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "EWORKSPACE", -4: "EUNSUPPORTED"}
 INFO = {0: "OK", 1: "ESKETCH", 2: "ECHOL", 3: "ECHOL2"}
-FP64, FP32_REFINE, BF16X2_REFINE = 0, 1, 2
+FP64, FP32_REFINE, BF16X2_REFINE, A1_FP32 = 0, 1, 2, 3
 SMOOTH = 0x100  # OR into precision: sample rows of the smoothed F A (rpcholqr.h, RPCHOLQR_SMOOTH)
 
 # Every function the header declares, with its ctypes signature.

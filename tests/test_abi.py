@@ -58,6 +58,10 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100_000, 65, 1536) > 0
     assert rq.workspace_bytes(100_000, 65, 1537) == 0
     assert rq.workspace_bytes(100_000, 100, 300, precision=rq.FP32_REFINE) == 0
+    # binary32 A1: the FP64 plan, n <= 64 only
+    assert rq.workspace_bytes(100_000, 64, 192, precision=rq.A1_FP32) == rq.workspace_bytes(100_000, 64, 192)
+    assert rq.workspace_bytes(100_000, 65, 195, precision=rq.A1_FP32) == 0
+    assert rq.workspace_bytes(100_000, 300, 900, precision=rq.A1_FP32) == 0
     assert rq.workspace_bytes(100_000, 64, 192, precision=rq.FP32_REFINE) > 0
     # 128 < n <= 512: the register panel sketch takes s <= 1536, the streaming
     # one s <= 8192; columns padded to 128k
