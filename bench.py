@@ -292,7 +292,7 @@ def main():
     def step():
         rq.factor(A, s, 0, Q=Q, R=R, workspace=ws, info=info, check=False)
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):  # at least one call, whose status is checked
         step()
     torch.cuda.synchronize()
     assert info.cpu().tolist() == [0, -1], info
@@ -403,7 +403,7 @@ def main():
         def step_refine():
             rq.factor(A, s, 0, Q=Q, R=R, workspace=ws_r, info=info, check=False, precision=prec)
 
-        for _ in range(args.warmup):
+        for _ in range(max(args.warmup, 1)):
             step_refine()
         torch.cuda.synchronize()
         assert info.cpu().tolist() == [0, -1], info

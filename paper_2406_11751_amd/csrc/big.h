@@ -391,6 +391,190 @@ __global__ __launch_bounds__(kGmThreads) void k_sketch_trail_gm(BigSketchArgs a)
   }
 }
 
+// Register form of the streaming sketch for 1536 < s <= 16 * 4 * 96: one wave
+// per column.  Lane (g, p) = (lane / 16, lane % 16) holds rows p + 16 t for
+// t = g L .. g L + L - 1 in W[0 .. L-1] (T = ceil(s / 16) <= 4 L), so the CR16
+// partial p, an fma chain over t = 0, 1, ..., is run by lane row 0 over its L
+// values, handed to row 1 (same p), and so on; row 3 ends with the 16 partials
+// and the same butterfly as elsewhere.  The reflector is staged in LDS.
+// Columns (waves) per panel: 8, or 4 (one wave per SIMD, so that the L = 96
+// column of 192 registers does not spill) for the largest samples.
+template <int L>
+constexpr int w_pw() { return L >= 96 ? 4 : 8; }
+
+template <int L>
+constexpr int w_rows() { return 16 * 4 * L; }
+
+// x from lane - 16 (the next lane row's predecessor); lanes 0..15 get lane 48..63's.
+__device__ __forceinline__ double from_row_above(double x, int lane) {
+  const int src = ((lane + 48) & 63) << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// The CR16 dot product of the wave's column with term(i) (an fma chain per
+// partial in ascending row, the four lane rows in turn), butterflied and
+// broadcast to the whole wave.
+template <int L, typename F>
+__device__ __forceinline__ double w_chain(int lane, F&& term) {
+  const int g = lane >> 4;
+  double acc = 0.0;
+#pragma unroll
+  for (int gg = 0; gg < 4; ++gg) {
+    if (g == gg) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) acc = term(i, acc);
+    }
+    if (gg < 3) {
+      const double up = from_row_above(acc, lane);
+      if (g == gg + 1) acc = up;
+    }
+  }
+  return readlane_d(row16_sum(acc), 48);
+}
+
+template <int L>
+__device__ __forceinline__ void w_load(double (&W)[L], const double* col, int lane, int s, bool have) {
+  const int g = lane >> 4, p = lane & 15;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int r = p + 16 * (g * L + i);
+    W[i] = (have && r < s) ? col[r] : 0.0;
+  }
+}
+
+// Apply reflector v (LDS, zero outside rows k .. s-1) with tau to the column:
+// returns the new values of rows k0 and k1 to the lanes holding them.
+template <int L>
+__device__ __forceinline__ void w_apply(double (&W)[L], const double* v, double tau, int lane, int k0, int k1,
+                                        double& keep0, double& keep1) {
+  const int g = lane >> 4, p = lane & 15;
+  const double tt = tau * w_chain<L>(lane, [&](int i, double acc) __attribute__((always_inline)) {
+    return __builtin_fma(v[p + 16 * (g * L + i)], W[i], acc);
+  });
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int r = p + 16 * (g * L + i);
+    W[i] = __builtin_fma(-tt, v[r], W[i]);
+    keep0 = (r == k0) ? W[i] : keep0;
+    keep1 = (r == k1) ? W[i] : keep1;
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(kWave * w_pw<L>()) void k_sketch_panel_w(BigSketchArgs a) {
+  constexpr int kWPW = w_pw<L>(), kWThreads = kWave * kWPW;
+  __shared__ double vbuf[2][w_rows<L>()];
+  __shared__ double tau_s[2];
+  __shared__ int bad[2];
+  const int n = a.n, s = a.s, c0 = a.c0;
+  if (c0 > 0 && a.info[0] != 0) return;  // an earlier panel failed
+  if (c0 == 0 && threadIdx.x == 0) {
+    a.info[0] = 0;
+    a.info[1] = -1;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int g = lane >> 4, p = lane & 15;
+  const int j = c0 + wave;  // my column
+  const int kend = min(c0 + kWPW, n);
+  double W[L];
+  w_load<L>(W, a.As + (int64_t)(j < n ? j : 0) * s, lane, s, j < n);
+  for (int e = threadIdx.x; e < 2 * w_rows<L>(); e += kWThreads) (&vbuf[0][0])[e] = 0.0;
+  if (threadIdx.x < 2) bad[threadIdx.x] = -1;
+  __syncthreads();
+
+  // Reflector k from my column (j == k); alpha = row k of it.
+  auto reflector = [&](int k, double alpha) __attribute__((always_inline)) {
+    const int buf = k & 1;
+    const double nu2 = w_chain<L>(lane, [&](int i, double acc) __attribute__((always_inline)) {
+      const double x = (p + 16 * (g * L + i) >= k) ? W[i] : 0.0;
+      return __builtin_fma(x, x, acc);
+    });
+    if (nu2 == 0.0 || !__builtin_isfinite(nu2)) {
+      if (lane == 0) bad[buf] = k;
+      return;
+    }
+    const double nu = __builtin_sqrt(nu2);
+    const double beta = (alpha >= 0.0) ? -nu : nu;
+    const double d = 1.0 / (alpha - beta);
+    const double tau = (beta - alpha) / beta;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int r = p + 16 * (g * L + i);
+      if (r < s) vbuf[buf][r] = (r >= k) ? ((r == k) ? 1.0 : W[i] * d) : 0.0;
+    }
+    if (lane == 0) {
+      tau_s[buf] = tau;
+      a.tau[k] = tau;
+      a.Rg[(int64_t)k * n + k] = beta;
+    }
+  };
+
+  if (wave == 0) reflector(c0, a.As[c0 + (int64_t)c0 * s]);  // row c0 of column c0 (c0 < n <= s)
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    if (bad[k & 1] >= 0) break;
+    const int buf = k & 1;
+    // Reflector k replaces sample column k, where the trailing-column kernel reads it.
+    for (int r = threadIdx.x; r < s; r += kWThreads) a.As[r + (int64_t)k * s] = vbuf[buf][r];
+    if (j > k && j < kend) {
+      double rk = 0.0, rk1 = 0.0;
+      w_apply<L>(W, vbuf[buf], tau_s[buf], lane, k, k + 1, rk, rk1);
+      const int holder = 16 * ((k >> 4) / L) + (k & 15);
+      if (lane == holder) a.Rg[(int64_t)k * n + j] = rk;
+      if (j == k + 1) reflector(k + 1, readlane_d(rk1, 16 * (((k + 1) >> 4) / L) + ((k + 1) & 15)));
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int b = bad[0] >= 0 ? bad[0] : bad[1];
+    if (b >= 0) {
+      a.info[0] = 1;  // ESKETCH
+      a.info[1] = b;
+    }
+  }
+}
+
+// Reflectors c0 .. kend-1 applied to the columns after the panel, one wave per
+// column, each reflector staged in LDS (double buffered).
+template <int L>
+__global__ __launch_bounds__(kWave * w_pw<L>()) void k_sketch_trail_w(BigSketchArgs a) {
+  constexpr int kWPW = w_pw<L>(), kWThreads = kWave * kWPW;
+  __shared__ double vbuf[2][w_rows<L>()];
+  if (a.info[0] != 0) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int n = a.n, s = a.s, c0 = a.c0;
+  const int kend = min(c0 + a.pw, n);
+  const int j = kend + kWPW * (int)blockIdx.x + wave;
+  double* col = a.As + (int64_t)(j < n ? j : 0) * s;
+  double W[L];
+  w_load<L>(W, col, lane, s, j < n);
+  auto stage = [&](int k, int buf) __attribute__((always_inline)) {
+    for (int e = threadIdx.x; e < w_rows<L>(); e += kWThreads) vbuf[buf][e] = (e < s) ? a.As[e + (int64_t)k * s] : 0.0;
+  };
+  stage(c0, 0);
+  __syncthreads();
+  for (int k = c0; k < kend; ++k) {
+    const int buf = (k - c0) & 1;
+    if (k + 1 < kend) stage(k + 1, buf ^ 1);  // buffer buf ^ 1 was last read in step k - 1
+    if (j < n) {
+      double rk = 0.0, unused = 0.0;
+      w_apply<L>(W, vbuf[buf], a.tau[k], lane, k, -1, rk, unused);
+      if (lane == 16 * ((k >> 4) / L) + (k & 15)) a.Rg[(int64_t)k * n + j] = rk;
+    }
+    __syncthreads();
+  }
+  if (j < n) {
+    const int g = lane >> 4, p = lane & 15;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int r = p + 16 * (g * L + i);
+      if (r < s) col[r] = W[i];
+    }
+  }
+}
+
 struct BigFinishArgs {
   int32_t n, nmax;
   const double* Rg;        // element (k, j) at Rg[k * rs_k + j * rs_j]
@@ -683,14 +867,16 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 // the results are stored only after a final barrier.  MFMA layout as in
 // k_passB: A operand T2(4 kc + l/16, 16 cb + l%16), B operand A1(row l%16,
 // 4 kc + l/16), result Q(row l%16, 16 cb + 4 v + l/16) in register v.
-// 16-row blocks per workgroup iteration (64 rows; one workgroup per CU, the
-// accumulators in AGPRs).
+// 16-row blocks per workgroup iteration: 64 rows with one workgroup per CU and
+// the accumulators in AGPRs; at nmax = 256, 32 rows with two workgroups per CU
+// (one's barriers and stage loads overlap the other's products: 11.9 -> 11.25 ms
+// at 4e6 x 256; at 384 and 512 the two-workgroup form does not fit the
+// registers).
 template <int NMAX>
-constexpr int passb_rows() { return 4; }
+constexpr int passb_rows() { return NMAX == 256 ? 2 : 4; }
 
-template <int NMAX>
-__global__ __launch_bounds__(kPassThreads, 1) void k_passB_big(PassBArgs a) {
-  constexpr int kBRows = passb_rows<NMAX>();
+template <int NMAX, int kBRows = passb_rows<NMAX>()>
+__global__ __launch_bounds__(kPassThreads, kBRows == 2 ? 2 : 1) void k_passB_big(PassBArgs a) {
   constexpr int NB = NMAX / 16, PERW = NB / kPassWaves;
   constexpr int SK = NMAX >= 384 ? 2 : 4;              // 4-wide k-chunks per stage (registers)
   constexpr int SR = 4 * SK;                           // T2 rows per stage

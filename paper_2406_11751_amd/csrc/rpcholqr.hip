@@ -103,6 +103,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, Plan* p, int64_t pa_cap = kPassA
 // Plan of the columns class 128 < n <= 512 (big.h).  nmax = 128 ceil(n/128).
 struct BigPlan {
   int nmax = 0, NB = 0, NP = 0, rpt = 0, ngroups = 0, nsplit = 0, G2 = 0;
+  int wl = 0;  // rpt == 0: rows per lane and lane row of the wave-per-column sketch (0: streaming)
   int64_t E = 0;
   size_t off_tri = 0, off_full = 0, off_T2 = 0, off_tri3 = 0, off_full3 = 0, off_Gg = 0, off_Rs = 0, off_Rg = 0,
          off_tau = 0, off_part = 0, off_part2 = 0, off_As = 0;
@@ -119,6 +120,8 @@ bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap =
   p->E = (int64_t)p->NB * (p->NB + 1) / 2 * 256;
   const int64_t rows = (s + 15) / 16;
   p->rpt = rows <= 16 ? 16 : rows <= 24 ? 24 : rows <= 32 ? 32 : rows <= 48 ? 48 : rows <= 64 ? 64 : rows <= 96 ? 96 : 0;
+  const int64_t wl = (rows + 3) / 4;
+  p->wl = p->rpt > 0 ? 0 : wl <= 32 ? 32 : wl <= 64 ? 64 : wl <= 96 ? 96 : 0;
   const int ng = p->nmax / kBigBlock;
   p->ngroups = ng * (ng + 1) / 2;
   const int64_t rblocks = (m + kGRows - 1) / kGRows;
@@ -410,7 +413,26 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     ba.tau = at_ws(p.off_tau);
     ba.Rg = at_ws(p.off_Rg);
     ba.info = inf;
-    if (p.rpt == 0) {
+    if (p.rpt == 0 && p.wl > 0) {
+      auto run = [&](auto wl) {
+        constexpr int L = decltype(wl)::value, kWPW = w_pw<L>(), kWThreads = kWave * kWPW;
+        ba.pw = kWPW;
+        for (int c0 = 0; c0 < n; c0 += kWPW) {
+          ba.c0 = c0;
+          hipLaunchKernelGGL((k_sketch_panel_w<L>), dim3(1), dim3(kWThreads), 0, st, ba);
+          const int64_t trail = n - std::min<int64_t>(c0 + kWPW, n);
+          if (trail > 0)
+            hipLaunchKernelGGL((k_sketch_trail_w<L>), dim3((unsigned)((trail + kWPW - 1) / kWPW)), dim3(kWThreads), 0,
+                               st, ba);
+        }
+      };
+      if (p.wl == 32)
+        run(std::integral_constant<int, 32>{});
+      else if (p.wl == 64)
+        run(std::integral_constant<int, 64>{});
+      else
+        run(std::integral_constant<int, 96>{});
+    } else if (p.rpt == 0) {
       ba.pw = kGmPW;
       for (int c0 = 0; c0 < n; c0 += kGmPW) {
         ba.c0 = c0;
@@ -530,9 +552,9 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     pb.ldq = ldq;
     pb.info = inf;
     with_big_nmax(p.nmax, [&](auto nm) {
-      constexpr int NM = decltype(nm)::value, rows = 16 * passb_rows<NM>();
+      constexpr int NM = decltype(nm)::value, RBK = passb_rows<NM>(), rows = 16 * RBK;
       const int64_t groups = (m + rows - 1) / rows;
-      const unsigned grid = (unsigned)std::min<int64_t>(groups, cus);
+      const unsigned grid = (unsigned)std::min<int64_t>(groups, (RBK == 2 ? 2 : 1) * cus);
       hipLaunchKernelGGL((k_passB_big<NM>), dim3(grid), dim3(kPassThreads), 0, st, pb);
     });
   }

@@ -118,7 +118,8 @@ WIDE_CASES = [
 # G in global memory and the MFMA pass B.  Ragged n (129, 200, 300), every
 # padded width (256, 384, 512), every sketch rows-per-lane class (32 .. 96),
 # the largest s of the register sketch, a single row-panel group, s = 2n; and
-# s = 1537 .. 8192 through the streaming sketch.
+# s = 1537 .. 6144 through the wave-per-column sketch (L = 32, 64, 96 rows per
+# lane row) and s = 6145 .. 8192 through the streaming sketch.
 BIG_CASES = [
     (3000, 129, 387, 1e8, 30),
     (20001, 200, 600, 1e12, 31),
@@ -135,6 +136,8 @@ BIG_CASES = [
     (30000, 300, 3000, 1e12, 51),   # s = 10n
     (12000, 512, 5120, 1e10, 52),   # s = 10n at the largest n
     (9000, 130, 8192, 1e4, 53),     # largest s, ragged n
+    (7000, 140, 6144, 1e7, 54),     # largest s of the wave-per-column sketch
+    (7000, 140, 6145, 1e7, 55),     # one row past it (streaming sketch)
 ]
 
 
