@@ -78,18 +78,49 @@ def counter_by_kernel(root: str, counter: str):
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
 
-def mfma_summary(stats_dir, mfma_dir, workload, command_stats, command_mfma, out_path):
+def counter_max_dispatch(root: str, counter: str):
+    """{kernel name: the counter summed over one dispatch, largest dispatch}."""
+    rows = list(csv.DictReader(open(_one("*counter_collection.csv", root))))
+    per = collections.defaultdict(float)
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            per[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
+    out = {}
+    for (k, _), v in per.items():
+        out[k] = max(out.get(k, 0.0), v)
+    return out
+
+
+def mfma_summary(stats_dir, mfma_dir, workload, command_stats, command_mfma, out_path, traffic=None):
     """Markdown table of the library's kernels: calls, average time, and the
-    derived MfmaUtil counter (MFMA busy cycles over active cycles of all SIMDs)."""
+    derived MfmaUtil counter (MFMA busy cycles over active cycles of all SIMDs).
+    With traffic = (fetch_dir, write_dir, fetch_scale, write_scale, commands),
+    also the HBM bytes read and written by the largest dispatch of each kernel."""
     stats = [s for s in kernel_stats(stats_dir) if "rpq::" in s["name"]]
     util = counter_by_kernel(mfma_dir, "MfmaUtil")
+    cmds = [command_stats, command_mfma] + (list(traffic[4]) if traffic else [])
+    head = "| kernel | calls | average us | total ms | MfmaUtil % |"
+    rule = "|---|---|---|---|---|"
+    if traffic:
+        fetch = counter_max_dispatch(traffic[0], "FETCH_SIZE")
+        write = counter_max_dispatch(traffic[1], "WRITE_SIZE")
+        head += " HBM read, largest dispatch (GB) | HBM written (GB) |"
+        rule += "---|---|"
     lines = [f"# rocprofv3: {workload}", "", "Kernel statistics and MFMA utilization, commands (repository root, MI355X):",
-             "", "```", command_stats, command_mfma, "```", "",
-             "| kernel | calls | average us | total ms | MfmaUtil % |", "|---|---|---|---|---|"]
+             "", "```", *cmds, "```", ""]
+    if traffic:
+        lines += [f"HBM bytes are FETCH_SIZE x {traffic[2]:.3f} and WRITE_SIZE x {traffic[3]:.3f} (the factors "
+                  "that make the counters of a plain 512 MiB device copy read 512 MiB).", ""]
+    lines += [head, rule]
     for s in sorted(stats, key=lambda s: -s["avg_us"] * s["calls"]):
         u = util.get(s["name"])
-        lines.append(f"| `{s['name']}` | {s['calls']} | {s['avg_us']:.1f} | {s['avg_us'] * s['calls'] / 1e3:.2f} | "
-                     + (f"{u:.1f}" if u is not None else "-") + " |")
+        row = (f"| `{s['name']}` | {s['calls']} | {s['avg_us']:.1f} | {s['avg_us'] * s['calls'] / 1e3:.2f} | "
+               + (f"{u:.1f}" if u is not None else "-") + " |")
+        if traffic:
+            f, w = fetch.get(s["name"]), write.get(s["name"])
+            row += (f" {f * 1024 * traffic[2] / 1e9:.2f} |" if f is not None else " - |")
+            row += (f" {w * 1024 * traffic[3] / 1e9:.2f} |" if w is not None else " - |")
+        lines.append(row)
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -131,8 +162,14 @@ def main():
     a = ap.parse_args()
     if a.mfma:
         os.makedirs(a.out, exist_ok=True)
+        traffic = None
+        if a.fetch and a.write and a.copy_fetch and a.copy_write:
+            _, (_, cf_kib) = _pick(counter_per_dispatch(a.copy_fetch, "FETCH_SIZE"), a.copy_kernel)
+            _, (_, cw_kib) = _pick(counter_per_dispatch(a.copy_write, "WRITE_SIZE"), a.copy_kernel)
+            traffic = (a.fetch, a.write, COPY_BYTES / (cf_kib * 1024.0), COPY_BYTES / (cw_kib * 1024.0),
+                       (a.command_fetch, a.command_write, a.command_copy))
         mfma_summary(a.stats, a.mfma, a.workload, a.command_stats, a.command_mfma,
-                     os.path.join(a.out, f"{a.tag}.md"))
+                     os.path.join(a.out, f"{a.tag}.md"), traffic)
         return
 
     stats = kernel_stats(a.stats)
