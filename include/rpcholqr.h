@@ -120,7 +120,7 @@ typedef struct {
 /* Cholesky of the second pass of a refined precision (G = Q1^T Q1) failed. */
 #define RPCHOLQR_INFO_ECHOL2 3
 
-/* Largest n the library accepts (512).  Supported sizes: n <= 512 for
+/* Largest n the library accepts (1024).  Supported sizes: n <= 1024 for
  * RPCHOLQR_FP64 with s <= 1536, and s <= 8192 when n > 128 (the sketch then
  * streams the sample from the workspace); n <= 64 for the refined precisions
  * and RPCHOLQR_A1_FP32;

@@ -1,4 +1,4 @@
-// Kernels for 128 < n <= 512 (Algorithm rpCholesky-QR lines 2-3 and Algorithm
+// Kernels for 128 < n <= 1024 (Algorithm rpCholesky-QR lines 2-3 and Algorithm
 // Preconditioned Cholesky-QR lines 2, 4 and 6), FP64.  Column counts are
 // padded to nmax, a multiple of 128 (identity beyond n in every triangle).
 //
@@ -33,7 +33,7 @@
 
 namespace rpq {
 
-constexpr int kBigMaxN = 512;
+constexpr int kBigMaxN = 1024;
 constexpr int kBigBlock = 128;                 // nmax is a multiple of this
 // Sketch panel width: one 16-lane group per panel column, 32 columns (512
 // threads), or 16 (256 threads, 512 registers per lane) when the sample
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 // CU takes 64 rows at a time; wave w owns the 16-column
 // blocks w, w + 4, ... (balanced over the triangle) for all four row blocks,
 // with the accumulators in AGPRs.  The contraction runs in stages of 16 rows
-// of T2 (four 4-wide k-chunks; 8 rows for nmax >= 384, so that a stage in
+// of T2 (four 4-wide k-chunks; 8 rows for nmax >= 384 and 4 beyond 768, so that a stage in
 // flight fits the registers): while a stage is multiplied from LDS, the next
 // stage of T2 and the next 16 columns of the rows' A1 are already being loaded
 // into registers; each stage is stored to the other LDS buffer after the
@@ -871,14 +871,20 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 // the accumulators in AGPRs; at nmax = 256, 32 rows with two workgroups per CU
 // (one's barriers and stage loads overlap the other's products: 11.9 -> 11.25 ms
 // at 4e6 x 256; at 384 and 512 the two-workgroup form does not fit the
-// registers).
+// registers); beyond 512 columns, 32 rows with one workgroup per CU (64 rows of
+// accumulators would exceed the AGPRs).
 template <int NMAX>
-constexpr int passb_rows() { return NMAX == 256 ? 2 : 4; }
+constexpr int passb_rows() { return NMAX == 256 || NMAX > 512 ? 2 : 4; }
+
+// Workgroups per CU of k_passB_big: two at nmax = 256 (32-row iterations),
+// else one (the accumulators take the AGPRs).
+template <int NMAX>
+constexpr int passb_occupancy() { return NMAX == 256 ? 2 : 1; }
 
 template <int NMAX, int kBRows = passb_rows<NMAX>()>
-__global__ __launch_bounds__(kPassThreads, kBRows == 2 ? 2 : 1) void k_passB_big(PassBArgs a) {
+__global__ __launch_bounds__(kPassThreads, passb_occupancy<NMAX>()) void k_passB_big(PassBArgs a) {
   constexpr int NB = NMAX / 16, PERW = NB / kPassWaves;
-  constexpr int SK = NMAX >= 384 ? 2 : 4;              // 4-wide k-chunks per stage (registers)
+  constexpr int SK = NMAX > 768 ? 1 : NMAX >= 384 ? 2 : 4;  // 4-wide k-chunks per stage (registers)
   constexpr int SR = 4 * SK;                           // T2 rows per stage
   constexpr int TLD = NMAX + 4;                        // LDS row stride of a T2 stage
   constexpr int TPT = SR * NMAX / kPassThreads;        // T2 stage values per thread

@@ -333,7 +333,11 @@ void with_big_nmax(int nmax, F&& fn) {
   switch (nmax) {
     case 256: fn(std::integral_constant<int, 256>{}); break;
     case 384: fn(std::integral_constant<int, 384>{}); break;
-    default: fn(std::integral_constant<int, 512>{}); break;
+    case 512: fn(std::integral_constant<int, 512>{}); break;
+    case 640: fn(std::integral_constant<int, 640>{}); break;
+    case 768: fn(std::integral_constant<int, 768>{}); break;
+    case 896: fn(std::integral_constant<int, 896>{}); break;
+    default: fn(std::integral_constant<int, 1024>{}); break;
   }
 }
 
@@ -552,9 +556,9 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     pb.ldq = ldq;
     pb.info = inf;
     with_big_nmax(p.nmax, [&](auto nm) {
-      constexpr int NM = decltype(nm)::value, RBK = passb_rows<NM>(), rows = 16 * RBK;
+      constexpr int NM = decltype(nm)::value, rows = 16 * passb_rows<NM>();
       const int64_t groups = (m + rows - 1) / rows;
-      const unsigned grid = (unsigned)std::min<int64_t>(groups, (RBK == 2 ? 2 : 1) * cus);
+      const unsigned grid = (unsigned)std::min<int64_t>(groups, passb_occupancy<NM>() * cus);
       hipLaunchKernelGGL((k_passB_big<NM>), dim3(grid), dim3(kPassThreads), 0, st, pb);
     });
   }

@@ -53,7 +53,7 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100_000, 32, 1536) > rq.workspace_bytes(100_000, 32, 96)
     assert rq.workspace_bytes(100_000, 32, 1537) == 0  # beyond the largest supported sample
     # 64 < n <= 128: FP64 only; the generic sketch kernel bounds s
-    assert rq.max_n() == 512
+    assert rq.max_n() == 1024
     assert rq.workspace_bytes(100_000, 128, 384) >= 384 * 128 * 8 + 128 * 128 * 8
     assert rq.workspace_bytes(100_000, 65, 1536) > 0
     assert rq.workspace_bytes(100_000, 65, 1537) == 0
@@ -63,7 +63,7 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(100_000, 65, 195, precision=rq.A1_FP32) == 0
     assert rq.workspace_bytes(100_000, 300, 900, precision=rq.A1_FP32) == 0
     assert rq.workspace_bytes(100_000, 64, 192, precision=rq.FP32_REFINE) > 0
-    # 128 < n <= 512: the register panel sketch takes s <= 1536, the streaming
+    # 128 < n <= 1024: the register panel sketch takes s <= 1536, the streaming
     # one s <= 8192; columns padded to 128k
     for n in (129, 256, 300, 512):
         assert rq.workspace_bytes(1_000_000, n, 3 * n) >= 3 * n * n * 8
@@ -73,7 +73,9 @@ def test_workspace_query_host_logic():
     assert rq.workspace_bytes(1_000_000, 300, 8192) > 0
     assert rq.workspace_bytes(1_000_000, 300, 8193) == 0
     assert rq.workspace_bytes(100, 129, 387) == 0       # m < n
-    assert rq.workspace_bytes(1_000_000, 513, 1539) == 0
+    assert rq.workspace_bytes(1_000_000, 513, 1539) > 0
+    assert rq.workspace_bytes(1_000_000, 1024, 3072) >= 3072 * 1024 * 8 + 4 * 1024 * 1024 * 8
+    assert rq.workspace_bytes(1_000_000, 1025, 3075) == 0
     # smoothing adds the chunk sums: ceil(m / chunk) * s * n doubles
     for m, n, s in ((1_000_000, 64, 192), (3000, 300, 900), (20_000_000, 16, 48)):
         chunk = 4096 * max(1, -(-(-(-m // 4096)) // 256))

@@ -141,7 +141,19 @@ BIG_CASES = [
 ]
 
 
-@pytest.mark.parametrize("m,n,s,kappa,seed", BIG_CASES)
+# 512 < n <= 1024: padded widths 640 .. 1024 (pass B on 32-row iterations, the
+# Cholesky with G in global memory, up to 36 Gram groups), s = 3n through the
+# wave-per-column sketch.
+WIDER_CASES = [
+    (4000, 513, 1539, 1e8, 60),
+    (3000, 640, 1920, 1e12, 61),
+    (5000, 768, 2304, 1e10, 62),
+    (3001, 1000, 3000, 1e6, 63),
+    (4000, 1024, 3072, 1e15, 64),
+]
+
+
+@pytest.mark.parametrize("m,n,s,kappa,seed", BIG_CASES + WIDER_CASES)
 def test_parity_big(m, n, s, kappa, seed):
     A_h = gen_usv(m, n, kappa, 100 + seed)
     _, _, orth, res = check_case(A_h, s, seed)

@@ -55,7 +55,7 @@ def test_sketch_preconditioner_reproduces_factor(m, n, s, kappa, seed):
 
 
 @pytest.mark.parametrize("m,n,kappa,seed", [(4000, 16, 1e6, 5), (10000, 50, 1e8, 6), (2500, 96, 1e10, 7),
-                                            (3000, 200, 1e10, 8)])
+                                            (3000, 200, 1e10, 8), (3000, 700, 1e8, 9)])
 def test_against_oracle_alg1_with_signed_preconditioner(m, n, kappa, seed):
     # A preconditioner that is not sign-normalized: the sketch's R_s with every
     # third row negated (Algorithm 1 takes any nonsingular upper triangular R_s).
