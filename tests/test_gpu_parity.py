@@ -454,3 +454,11 @@ def test_parity_full_size_1e6x128(kappa):
     Qh, Rh, orth, res = check_case(A_h, s, 0)
     print(f"  kappa={kappa:.0e}: orth={orth:.3e} residual={res:.3e}", flush=True)
     assert orth <= 1e-12 and res <= 1e-15
+
+
+def test_parity_small_reference_configuration():
+    # The small single-matrix workload exactly: 10,000 x 50, s = 3n = 150,
+    # kappa = 1e8, matrix seed 0, sampling seed 0.
+    A_h = gen_usv(10_000, 50, 1e8, 0)
+    _, _, orth, res = check_case(A_h, 150, 0)
+    assert orth <= 1e-12 and res <= 1e-15
