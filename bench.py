@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the refined-precision measurement")
     ap.add_argument("--batched-steps", type=int, default=10)
-    ap.add_argument("--no-large", action="store_true", help="skip the 4e6 x 256 and 1.6e7 x 512 workloads")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1e6 x 128, 4e6 x 256 and 1.6e7 x 512 workloads")
     ap.add_argument("--large-only", default="", help="comma-separated subset of the large workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (for counter calibration)")
@@ -176,8 +176,9 @@ def batched_measurement(args, torch, rq, gen_usv, metrics):
 
 
 def large_measurement(args, torch, rq, metrics):
-    """The 4,000,000 x 256 (kappa 1e12, s = 768) and 16,000,000 x 512 (kappa 1e10,
-    s = 1536 and s = 5120) workloads in FP64, generated on the GPU (the larger one with the
+    """The 1,000,000 x 128 (kappa 1e8, s = 384), 4,000,000 x 256 (kappa 1e12, s = 768)
+    and 16,000,000 x 512 (kappa 1e10, s = 1536 and s = 5120) workloads in FP64,
+    generated on the GPU (the largest with the
     polar-factor construction, which needs no second m x n buffer).  Reports time
     per factorization, GB/s on 24mn, TFLOP/s on 3mn^2 and its fraction of the
     FP64 peak, orthogonality and residual at full size, and parity against the
@@ -190,7 +191,8 @@ def large_measurement(args, torch, rq, metrics):
     dev = torch.device("cuda:0")
     res = {}
     A, made = None, None
-    for name, m, n, s, kappa, steps in (("4e6x256", 4_000_000, 256, 768, 1e12, 10),
+    for name, m, n, s, kappa, steps in (("1e6x128", 1_000_000, 128, 384, 1e8, 20),
+                                        ("4e6x256", 4_000_000, 256, 768, 1e12, 10),
                                         ("1.6e7x512", 16_000_000, 512, 1536, 1e10, 3),
                                         ("1.6e7x512_s10n", 16_000_000, 512, 5120, 1e10, 3)):
         if args.large_only and name not in args.large_only.split(","):
