@@ -263,7 +263,7 @@ def test_deterministic_bits_wide():
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
-@pytest.mark.parametrize("m,n,s", [(50000, 64, 192), (20000, 100, 300)])
+@pytest.mark.parametrize("m,n,s", [(50000, 64, 192), (20000, 100, 300), (20000, 300, 900), (8000, 200, 2000)])
 def test_single_call_graph_capture(m, n, s):
     # rpcholqr_factor issues kernels only (no allocation, no memset), so a call
     # can be captured; every replay must give the eager result.
@@ -291,10 +291,11 @@ def test_single_call_graph_capture(m, n, s):
         assert torch.equal(Q, Q0) and torch.equal(R, R0), f"replay {rep}"
 
 
-@pytest.mark.parametrize("pad,off,n", [(13, 0, 24), (14, 0, 24), (14, 1, 24), (13, 0, 100), (14, 1, 100)])
+@pytest.mark.parametrize("pad,off,n", [(13, 0, 24), (14, 0, 24), (14, 1, 24), (13, 0, 100), (14, 1, 100),
+                                       (13, 0, 300), (14, 1, 300)])
 def test_leading_dimensions(pad, off, n):
     # Odd and even leading dimensions, and an A that starts 8 bytes into its
-    # allocation, for a 64-column class and the 128-column class.
+    # allocation, for a 64-column class, the 128-column class and n > 128.
     m = 3001
     s = 3 * n
     A_h = gen_usv(m, n, 1e6, 4)
