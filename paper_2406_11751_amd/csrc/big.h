@@ -744,6 +744,7 @@ struct BigGramArgs {
 };
 
 constexpr int kGRows = 32;
+constexpr int kXcds = 8;  // accelerator complex dies of the device, each with its own L2
 constexpr int kGLd = 2 * kBigBlock + 4;  // LDS row stride of the staged strips
 
 template <bool DIAG, int WV>
@@ -828,7 +829,19 @@ __device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int 
 __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
   __shared__ double xs[kGRows * kGLd];
   if (a.info[0] != 0) return;
-  const int gi = blockIdx.x % a.ngroups, split = blockIdx.x / a.ngroups;
+  // Workgroups are dispatched to the 8 XCDs round robin (XCD = blockIdx mod 8),
+  // each XCD with its own L2.  When nsplit is a multiple of 8, the ngroups
+  // workgroups of one row split are given consecutive dispatch slots of one
+  // XCD, so that they read the same rows of A1 through the same L2.
+  int gi, split;
+  if (a.nsplit % kXcds == 0) {
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    split = xcd + kXcds * (slot / a.ngroups);
+    gi = slot % a.ngroups;
+  } else {
+    gi = blockIdx.x % a.ngroups;
+    split = blockIdx.x / a.ngroups;
+  }
   const int NG = a.nmax / kBigBlock;
   int I = 0, rem = gi;
   while (rem >= NG - I) {

@@ -127,6 +127,7 @@ bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap =
   const int64_t rblocks = (m + kGRows - 1) / kGRows;
   int64_t ns = (1024 + p->ngroups - 1) / p->ngroups;
   ns = std::min<int64_t>(std::min<int64_t>(ns, rblocks), std::min<int64_t>(pa_cap, kPassAMaxBlocks));
+  if (ns >= kXcds) ns -= ns % kXcds;  // XCD-aware Gram schedule (k_gram_big)
   p->nsplit = (int)std::max<int64_t>(ns, 1);
   p->G2 = (p->nsplit + kReduceChunk - 1) / kReduceChunk;
   const size_t d = sizeof(double), nm = (size_t)p->nmax;
