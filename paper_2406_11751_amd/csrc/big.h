@@ -868,107 +868,124 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 }
 
 // Line 6: Q = A1 R2^{-1} with the explicit inverse T2 (nmax x nmax row-major,
-// zero outside the n x n upper triangle), in place over A1.  One workgroup per
-// CU takes 64 rows at a time; wave w owns the 16-column
-// blocks w, w + 4, ... (balanced over the triangle) for all four row blocks,
-// with the accumulators in AGPRs.  The contraction runs in stages of 16 rows
-// of T2 (four 4-wide k-chunks; 8 rows for nmax >= 384 and 4 beyond 768, so that a stage in
-// flight fits the registers): while a stage is multiplied from LDS, the next
-// stage of T2 and the next 16 columns of the rows' A1 are already being loaded
-// into registers; each stage is stored to the other LDS buffer after the
-// multiply, then one barrier.  All waves read every column of the rows, so
-// the results are stored only after a final barrier.  MFMA layout as in
-// k_passB: A operand T2(4 kc + l/16, 16 cb + l%16), B operand A1(row l%16,
-// 4 kc + l/16), result Q(row l%16, 16 cb + 4 v + l/16) in register v.
-// 16-row blocks per workgroup iteration: 64 rows with one workgroup per CU and
-// the accumulators in AGPRs; at nmax = 256, 32 rows with two workgroups per CU
-// (one's barriers and stage loads overlap the other's products: 11.9 -> 11.25 ms
-// at 4e6 x 256; at 384 and 512 the two-workgroup form does not fit the
-// registers); beyond 512 columns, 32 rows with one workgroup per CU (64 rows of
-// accumulators would exceed the AGPRs).
+// zero outside the n x n upper triangle), in place over A1.  One workgroup of
+// eight waves per CU (two per SIMD) takes 16 * passb_rows rows at a time;
+// wave w owns the 16-column blocks w, w + 8, ... (balanced over the
+// triangle) for all row blocks, with at most 64 accumulators per lane.  The
+// contraction runs in stages of passb_chunks 4-wide k-chunks.  Each wave
+// loads its own operands straight into registers, one stage ahead: its T2
+// blocks from L2 through a buffer descriptor (each T2 element is used by one
+// wave per row group, so staging it in LDS would only add a barrier per
+// stage) and the rows' A1.  The only barrier is at the end of a row group:
+// all waves read every column of the rows, so the results are stored over
+// A1 only after it.  MFMA layout as in k_passB: A operand T2(4 kc + l/16,
+// 16 cb + l%16), B operand A1(row l%16, 4 kc + l/16), result Q(row l%16,
+// 16 cb + 4 v + l/16) in register v.  Each accumulator receives its
+// k-chunks in ascending order, so Q is the same to the bit for any shape.
+// Row blocks per iteration: 64 accumulators per lane at most (48 rows at
+// nmax = 512, where 64 rows would leave too few registers for the stage in
+// flight); 4-wide k-chunks per stage: two up to 512 columns, else one.
+constexpr int kPassBBigWaves = 8;
 template <int NMAX>
-constexpr int passb_rows() { return NMAX == 256 || NMAX > 512 ? 2 : 4; }
-
-// Workgroups per CU of k_passB_big: two at nmax = 256 (32-row iterations),
-// else one (the accumulators take the AGPRs).
+constexpr int passb_rows() { return NMAX == 512 ? 3 : 2048 / NMAX < 4 ? 2048 / NMAX : 4; }
 template <int NMAX>
-constexpr int passb_occupancy() { return NMAX == 256 ? 2 : 1; }
+constexpr int passb_chunks() { return NMAX > 512 ? 1 : 2; }
 
 template <int NMAX, int kBRows = passb_rows<NMAX>()>
-__global__ __launch_bounds__(kPassThreads, passb_occupancy<NMAX>()) void k_passB_big(PassBArgs a) {
-  constexpr int NB = NMAX / 16, PERW = NB / kPassWaves;
-  constexpr int SK = NMAX > 768 ? 1 : NMAX >= 384 ? 2 : 4;  // 4-wide k-chunks per stage (registers)
-  constexpr int SR = 4 * SK;                           // T2 rows per stage
-  constexpr int TLD = NMAX + 4;                        // LDS row stride of a T2 stage
-  constexpr int TPT = SR * NMAX / kPassThreads;        // T2 stage values per thread
-  __shared__ double ts[2][SR * TLD];
+__global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs a) {
+  constexpr int WAVES = kPassBBigWaves;
+  constexpr int NB = NMAX / 16, PERW = NB / WAVES;
+  constexpr int SK = passb_chunks<NMAX>();   // 4-wide k-chunks per stage
+  constexpr int SR = 4 * SK;                 // T2 rows per stage
+  static_assert(NB % WAVES == 0, "pass B shape");
   if (a.info[0] != 0) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i16 = lane & 15, g4 = lane >> 4;
   const int n = a.n;
   const int nstage = (n + SR - 1) / SR;
   const int64_t groups = (a.m + 16 * kBRows - 1) / (16 * kBRows);
-  double tv[TPT];               // next T2 stage
-  double bv[SK][kBRows];        // next stage of A1: SK k-chunks x row blocks
-  auto fetch = [&](int64_t rbase, int st) __attribute__((always_inline)) {
-    const double* t2 = a.T2 + (int64_t)SR * st * NMAX + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) tv[u] = (st < nstage) ? t2[u * kPassThreads] : 0.0;
+  // T2 through a buffer resource: the lane's byte offset in one VGPR, the
+  // (k-chunk, column block) offset in an SGPR
+  const __amdgpu_buffer_rsrc_t t2r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.T2, (short)0, NMAX * NMAX * (int)sizeof(double), 0x00020000);
+  const int t2_lane = (g4 * NMAX + 16 * wave + i16) * (int)sizeof(double);
+  double un[SK][PERW];    // next stage: T2(4 kc + l/16, 16 cb + l%16) of the wave's blocks
+  double bn[SK][kBRows];  // next stage: A1(row l%16, 4 kc + l/16) of the row blocks
+  // Every load is unconditional, so that no wait for a load in flight is
+  // needed before the next stage: a T2 block left of the diagonal reads 0
+  // through an offset past the end of the buffer (no memory access), and A1
+  // is read at a row and column clamped into the matrix (rows past m only
+  // reach accumulator rows that are never stored; columns past n are zeroed
+  // where the last stage takes its operands).
+  constexpr int kT2Past = NMAX * NMAX * (int)sizeof(double);
+  auto fetch = [&](int64_t grp, int st) __attribute__((always_inline)) {
+    const int64_t rbase = grp * 16 * kBRows;
 #pragma unroll
     for (int kk = 0; kk < SK; ++kk) {
-      const int col = SR * st + 4 * kk + g4;
+      const int kc = SK * st + kk;
+#pragma unroll
+      for (int i = 0; i < PERW; ++i) {
+        const int cb = wave + WAVES * i;
+        const int off = cb >= (kc >> 2) ? (4 * kc * NMAX + 16 * WAVES * i) * (int)sizeof(double) : kT2Past;
+        un[kk][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(t2r, t2_lane, off, 0));
+      }
+      const int col = min(4 * kc + g4, n - 1);
 #pragma unroll
       for (int rb = 0; rb < kBRows; ++rb) {
-        const int64_t row = rbase + 16 * rb + i16;
-        bv[kk][rb] = (st < nstage && row < a.m && col < n) ? a.Q[row + (int64_t)col * a.ldq] : 0.0;
+        const int64_t row = min(rbase + 16 * rb + i16, a.m - 1);
+        bn[kk][rb] = a.Q[row + (int64_t)col * a.ldq];
       }
     }
   };
-  auto put = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      const int e = threadIdx.x + u * kPassThreads;
-      ts[buf][(e / NMAX) * TLD + e % NMAX] = tv[u];
-    }
-  };
-  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+  int64_t grp = blockIdx.x;
+  if (grp >= groups) return;
+  fetch(grp, 0);
+  for (; grp < groups; grp += gridDim.x) {
     const int64_t rbase = grp * 16 * kBRows;
     d4 acc[kBRows][PERW];
 #pragma unroll
     for (int rb = 0; rb < kBRows; ++rb)
 #pragma unroll
       for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
-    fetch(rbase, 0);
-    __syncthreads();  // the previous iteration's readers of ts are done
-    put(0);
-    __syncthreads();
     for (int st = 0; st < nstage; ++st) {
-      const int buf = st & 1;
-      double b[SK][kBRows];
+      double u[SK][PERW], b[SK][kBRows];
 #pragma unroll
-      for (int kk = 0; kk < SK; ++kk)
+      for (int kk = 0; kk < SK; ++kk) {
 #pragma unroll
-        for (int rb = 0; rb < kBRows; ++rb) b[kk][rb] = bv[kk][rb];
-      fetch(rbase, st + 1);
-      const double* tr = &ts[buf][g4 * TLD + i16];
+        for (int i = 0; i < PERW; ++i) u[kk][i] = un[kk][i];
+#pragma unroll
+        for (int rb = 0; rb < kBRows; ++rb) b[kk][rb] = bn[kk][rb];
+      }
+      if (SR * (st + 1) > n) {  // the last stage: columns past n (clamped reads) are zero
+#pragma unroll
+        for (int kk = 0; kk < SK; ++kk)
+#pragma unroll
+          for (int rb = 0; rb < kBRows; ++rb)
+            if (SR * st + 4 * kk + g4 >= n) b[kk][rb] = 0.0;
+      }
+      // the next stage (the first of the next row group after the last) is in
+      // flight while this one is multiplied
+      if (st + 1 < nstage)
+        fetch(grp, st + 1);
+      else if (grp + gridDim.x < groups)
+        fetch(grp + gridDim.x, 0);
 #pragma unroll
       for (int kk = 0; kk < SK; ++kk) {
         const int kc = SK * st + kk;
 #pragma unroll
         for (int i = 0; i < PERW; ++i) {
-          const int cb = wave + kPassWaves * i;
-          if (cb >= (kc >> 2)) {  // T2 is zero left of its diagonal
-            const double u = tr[4 * kk * TLD + 16 * cb];
+          const int cb = wave + WAVES * i;
+          if (cb >= (kc >> 2)) {
 #pragma unroll
             for (int rb = 0; rb < kBRows; ++rb)
-              acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[kk][rb], acc[rb][i], 0, 0, 0);
+              acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[kk][i], b[kk][rb], acc[rb][i], 0, 0, 0);
           }
         }
       }
-      if (st + 1 < nstage) put(buf ^ 1);
-      __syncthreads();
     }
-    // every wave has read these rows of A1 (the last barrier above)
+    // every wave has read all columns of these rows of A1 before any is overwritten
+    __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < kBRows; ++rb) {
       const int64_t row = rbase + 16 * rb + i16;
@@ -977,7 +994,7 @@ __global__ __launch_bounds__(kPassThreads, passb_occupancy<NMAX>()) void k_passB
         for (int i = 0; i < PERW; ++i)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int col = 16 * (wave + kPassWaves * i) + 4 * v + g4;
+            const int col = 16 * (wave + WAVES * i) + 4 * v + g4;
             if (col < n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
           }
       }

@@ -559,8 +559,8 @@ int32_t factor_big(int64_t m, int64_t n, int64_t s, uint64_t seed, const double*
     with_big_nmax(p.nmax, [&](auto nm) {
       constexpr int NM = decltype(nm)::value, rows = 16 * passb_rows<NM>();
       const int64_t groups = (m + rows - 1) / rows;
-      const unsigned grid = (unsigned)std::min<int64_t>(groups, passb_occupancy<NM>() * cus);
-      hipLaunchKernelGGL((k_passB_big<NM>), dim3(grid), dim3(kPassThreads), 0, st, pb);
+      const unsigned grid = (unsigned)std::min<int64_t>(groups, cus);
+      hipLaunchKernelGGL((k_passB_big<NM>), dim3(grid), dim3(64 * kPassBBigWaves), 0, st, pb);
     });
   }
   if (!launched()) return RPCHOLQR_EHIP;
