@@ -870,26 +870,41 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
 // Line 6: Q = A1 R2^{-1} with the explicit inverse T2 (nmax x nmax row-major,
 // zero outside the n x n upper triangle), in place over A1.  One workgroup of
 // eight waves per CU (two per SIMD) takes 16 * passb_rows rows at a time;
-// wave w owns the 16-column blocks w, w + 8, ... (balanced over the
-// triangle) for all row blocks, with at most 64 accumulators per lane.  The
-// contraction runs in stages of passb_chunks 4-wide k-chunks.  Each wave
-// loads its own operands straight into registers, one stage ahead: its T2
-// blocks from L2 through a buffer descriptor (each T2 element is used by one
-// wave per row group, so staging it in LDS would only add a barrier per
-// stage) and the rows' A1.  The only barrier is at the end of a row group:
-// all waves read every column of the rows, so the results are stored over
-// A1 only after it.  MFMA layout as in k_passB: A operand T2(4 kc + l/16,
+// wave w owns 16-column blocks in snake order (passb_block) for all row
+// blocks, with at most 64 accumulators per lane.  The contraction runs in
+// stages of passb_chunks 4-wide k-chunks.  Each wave loads its own operands
+// straight into registers: its T2 blocks from L2 through a buffer descriptor
+// (each T2 element is used by one wave per row group, so staging it in LDS
+// would only add a barrier per stage) and the rows' A1, into a ring of
+// passb_depth stages, each slot refilled right after its products, so a
+// load has passb_depth - 1 stages of products to arrive.  The stage loop
+// runs over this workgroup's row groups back to back (the ring crosses from
+// one group into the next) and is unrolled by the ring depth, so that every
+// slot is a fixed set of registers.  The only barrier is at the end of a row
+// group: all waves read every column of the rows, so the results are stored
+// over A1 only after it.  MFMA layout as in k_passB: A operand T2(4 kc + l/16,
 // 16 cb + l%16), B operand A1(row l%16, 4 kc + l/16), result Q(row l%16,
 // 16 cb + 4 v + l/16) in register v.  Each accumulator receives its
 // k-chunks in ascending order, so Q is the same to the bit for any shape.
 // Row blocks per iteration: 64 accumulators per lane at most (48 rows at
-// nmax = 512, where 64 rows would leave too few registers for the stage in
-// flight); 4-wide k-chunks per stage: two up to 512 columns, else one.
+// nmax = 512, where 64 rows would leave too few registers for the stages in
+// flight); 4-wide k-chunks per stage: two up to 512 columns, else one; ring
+// depth: as many stages as fit the 256 registers of a lane without spilling.
 constexpr int kPassBBigWaves = 8;
 template <int NMAX>
 constexpr int passb_rows() { return NMAX == 512 ? 3 : 2048 / NMAX < 4 ? 2048 / NMAX : 4; }
 template <int NMAX>
 constexpr int passb_chunks() { return NMAX > 512 ? 1 : 2; }
+template <int NMAX>
+constexpr int passb_depth() { return NMAX == 1024 ? 2 : (NMAX == 384 || NMAX == 512 || NMAX == 896) ? 4 : 5; }
+
+// Column block i of wave w, in snake order (w, 2W - 1 - w, 2W + w, ...): block
+// cb carries 4 (cb + 1) k-chunks of the triangle, so every wave gets the same
+// total when the blocks per wave are even.
+template <int WAVES>
+__device__ __forceinline__ int passb_block(int wave, int i) {
+  return WAVES * i + ((i & 1) ? WAVES - 1 - wave : wave);
+}
 
 template <int NMAX, int kBRows = passb_rows<NMAX>()>
 __global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs a) {
@@ -897,6 +912,7 @@ __global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs 
   constexpr int NB = NMAX / 16, PERW = NB / WAVES;
   constexpr int SK = passb_chunks<NMAX>();   // 4-wide k-chunks per stage
   constexpr int SR = 4 * SK;                 // T2 rows per stage
+  constexpr int D = passb_depth<NMAX>();     // stages in flight
   static_assert(NB % WAVES == 0, "pass B shape");
   if (a.info[0] != 0) return;
   const int lane = threadIdx.x & (kWave - 1);
@@ -905,99 +921,101 @@ __global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs 
   const int n = a.n;
   const int nstage = (n + SR - 1) / SR;
   const int64_t groups = (a.m + 16 * kBRows - 1) / (16 * kBRows);
-  // T2 through a buffer resource: the lane's byte offset in one VGPR, the
-  // (k-chunk, column block) offset in an SGPR
+  if ((int64_t)blockIdx.x >= groups) return;
+  const int64_t my_groups = (groups - blockIdx.x + gridDim.x - 1) / gridDim.x;
+  const int64_t nsteps = (my_groups * nstage + D - 1) / D * D;  // padded to whole rings
   const __amdgpu_buffer_rsrc_t t2r =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.T2, (short)0, NMAX * NMAX * (int)sizeof(double), 0x00020000);
-  const int t2_lane = (g4 * NMAX + 16 * wave + i16) * (int)sizeof(double);
-  double un[SK][PERW];    // next stage: T2(4 kc + l/16, 16 cb + l%16) of the wave's blocks
-  double bn[SK][kBRows];  // next stage: A1(row l%16, 4 kc + l/16) of the row blocks
-  // Every load is unconditional, so that no wait for a load in flight is
-  // needed before the next stage: a T2 block left of the diagonal reads 0
-  // through an offset past the end of the buffer (no memory access), and A1
-  // is read at a row and column clamped into the matrix (rows past m only
-  // reach accumulator rows that are never stored; columns past n are zeroed
-  // where the last stage takes its operands).
+  const int t2_lane = (g4 * NMAX + i16) * (int)sizeof(double);
   constexpr int kT2Past = NMAX * NMAX * (int)sizeof(double);
-  auto fetch = [&](int64_t grp, int st) __attribute__((always_inline)) {
+  double U[D][SK][PERW];    // ring of stages: T2(4 kc + l/16, 16 cb + l%16) of the wave's blocks
+  double B[D][SK][kBRows];  // and A1(row l%16, 4 kc + l/16) of the row blocks
+  auto fetch = [&](int slot, int64_t grp, int st) __attribute__((always_inline)) {
     const int64_t rbase = grp * 16 * kBRows;
 #pragma unroll
     for (int kk = 0; kk < SK; ++kk) {
       const int kc = SK * st + kk;
 #pragma unroll
       for (int i = 0; i < PERW; ++i) {
-        const int cb = wave + WAVES * i;
-        const int off = cb >= (kc >> 2) ? (4 * kc * NMAX + 16 * WAVES * i) * (int)sizeof(double) : kT2Past;
-        un[kk][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(t2r, t2_lane, off, 0));
+        const int cb = passb_block<WAVES>(wave, i);
+        const int off = cb >= (kc >> 2) ? (4 * kc * NMAX + 16 * cb) * (int)sizeof(double) : kT2Past;
+        U[slot][kk][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(t2r, t2_lane, off, 0));
       }
       const int col = min(4 * kc + g4, n - 1);
 #pragma unroll
       for (int rb = 0; rb < kBRows; ++rb) {
         const int64_t row = min(rbase + 16 * rb + i16, a.m - 1);
-        bn[kk][rb] = a.Q[row + (int64_t)col * a.ldq];
+        B[slot][kk][rb] = a.Q[row + (int64_t)col * a.ldq];
       }
     }
   };
-  int64_t grp = blockIdx.x;
-  if (grp >= groups) return;
-  fetch(grp, 0);
-  for (; grp < groups; grp += gridDim.x) {
-    const int64_t rbase = grp * 16 * kBRows;
-    d4 acc[kBRows][PERW];
+  // stage counters: (grp_c, st_c) consumed now, (grp_f, st_f) fetched now (D later)
+  int64_t grp_c = blockIdx.x, grp_f = blockIdx.x;
+  int st_c = 0, st_f = 0;
+  auto advance = [&](int64_t& grp, int& st) __attribute__((always_inline)) {
+    if (++st == nstage) {
+      st = 0;
+      grp += gridDim.x;
+    }
+  };
 #pragma unroll
-    for (int rb = 0; rb < kBRows; ++rb)
+  for (int j = 0; j < D; ++j) {
+    fetch(j, grp_f, st_f);
+    advance(grp_f, st_f);
+  }
+  d4 acc[kBRows][PERW];
+  for (int64_t g0 = 0; g0 < nsteps; g0 += D) {
 #pragma unroll
-      for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int st = 0; st < nstage; ++st) {
-      double u[SK][PERW], b[SK][kBRows];
+    for (int j = 0; j < D; ++j) {
+      const int st = st_c;
+      if (st == 0) {
 #pragma unroll
-      for (int kk = 0; kk < SK; ++kk) {
+        for (int rb = 0; rb < kBRows; ++rb)
 #pragma unroll
-        for (int i = 0; i < PERW; ++i) u[kk][i] = un[kk][i];
-#pragma unroll
-        for (int rb = 0; rb < kBRows; ++rb) b[kk][rb] = bn[kk][rb];
+          for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
       }
       if (SR * (st + 1) > n) {  // the last stage: columns past n (clamped reads) are zero
 #pragma unroll
         for (int kk = 0; kk < SK; ++kk)
 #pragma unroll
           for (int rb = 0; rb < kBRows; ++rb)
-            if (SR * st + 4 * kk + g4 >= n) b[kk][rb] = 0.0;
+            if (SR * st + 4 * kk + g4 >= n) B[j][kk][rb] = 0.0;
       }
-      // the next stage (the first of the next row group after the last) is in
-      // flight while this one is multiplied
-      if (st + 1 < nstage)
-        fetch(grp, st + 1);
-      else if (grp + gridDim.x < groups)
-        fetch(grp + gridDim.x, 0);
 #pragma unroll
       for (int kk = 0; kk < SK; ++kk) {
         const int kc = SK * st + kk;
 #pragma unroll
         for (int i = 0; i < PERW; ++i) {
-          const int cb = wave + WAVES * i;
-          if (cb >= (kc >> 2)) {
+          const int cb = passb_block<WAVES>(wave, i);
+          if (cb >= (kc >> 2)) {  // T2 is zero left of its diagonal (a wave-uniform test)
 #pragma unroll
             for (int rb = 0; rb < kBRows; ++rb)
-              acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[kk][i], b[kk][rb], acc[rb][i], 0, 0, 0);
+              acc[rb][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(U[j][kk][i], B[j][kk][rb], acc[rb][i], 0, 0, 0);
           }
         }
       }
-    }
-    // every wave has read all columns of these rows of A1 before any is overwritten
-    __syncthreads();
+      // the slot is free again: it takes the stage D - 1 stages after the next
+      fetch(j, grp_f, st_f);
+      advance(grp_f, st_f);
+      if (st == nstage - 1) {
+        // every wave has read all columns of these rows of A1 before any is overwritten
+        __syncthreads();
+        const int64_t rbase = grp_c * 16 * kBRows;
 #pragma unroll
-    for (int rb = 0; rb < kBRows; ++rb) {
-      const int64_t row = rbase + 16 * rb + i16;
-      if (row < a.m) {
+        for (int rb = 0; rb < kBRows; ++rb) {
+          const int64_t row = rbase + 16 * rb + i16;
+          if (row < a.m) {
 #pragma unroll
-        for (int i = 0; i < PERW; ++i)
+            for (int i = 0; i < PERW; ++i)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = 16 * (wave + WAVES * i) + 4 * v + g4;
-            if (col < n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
+              for (int v = 0; v < 4; ++v) {
+                const int col = 16 * passb_block<WAVES>(wave, i) + 4 * v + g4;
+                if (col < n) a.Q[row + (int64_t)col * a.ldq] = acc[rb][i][v];
+              }
           }
+        }
       }
+      advance(grp_c, st_c);
     }
   }
 }
