@@ -654,13 +654,17 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
   for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
     const int64_t r0 = (pg * kPassWaves + wave) * kWave;
     const bool valid = r0 + lane < a.m;
-    // -A1(rows, k-chunk it) for the four row blocks
+    // A1(rows, k-chunk it) for the four row blocks.  The loads are
+    // unconditional (a conditional load would make the compiler wait for the
+    // ones in flight): rows past m are read at row m - 1 and only reach rows
+    // that are never stored; chunks past the update (it >= nit, prefetched at
+    // the end) are read at clamped columns and never used.
     auto fetch_b = [&](int it, double (&dst)[4]) __attribute__((always_inline)) {
-      const int col = 4 * it + g;  // < 64 P <= n - 1 when it < nit
+      const int col = min(4 * it + g, a.n - 1);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
-        const int64_t row = r0 + 16 * rb + i16;
-        dst[rb] = (it < nit && row < a.m) ? -a.W[row + (int64_t)col * a.ldw] : 0.0;
+        const int64_t row = min(r0 + 16 * rb + i16, a.m - 1);
+        dst[rb] = a.W[row + (int64_t)col * a.ldw];
       }
     };
     double ring[kDepth][4];
@@ -672,15 +676,18 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
       int64_t lda = a.lda;
       asm volatile("" : "+s"(nc), "+s"(lda));
       const double* Ap = a.A + (int64_t)c0 * lda;
+      // unconditional loads as above: columns past the panel's last (nc) only
+      // reach solve columns past it, which are never stored (U is the
+      // identity beyond n)
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
-        const int64_t row = r0 + 16 * rb + i16;
+        const int64_t row = min(r0 + 16 * rb + i16, a.m - 1);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int col = 16 * cb + 4 * v + g;
-            acc[rb][cb][v] = (row < a.m && col < nc) ? Ap[row + (int64_t)col * lda] : 0.0;
+            const int col = min(16 * cb + 4 * v + g, nc - 1);
+            acc[rb][cb][v] = Ap[row + (int64_t)col * lda];
           }
       }
     }
@@ -700,7 +707,8 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
         fetch_b(16 * Qb + kc + kDepth, ring[kc % kDepth]);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          const double u = uq[4 * kc * kR12Ld + 16 * cb];
+          // -U: fma(-u, b, acc) rounds as fma(u, -b, acc), the update -A1(:, k) U(k, :)
+          const double u = -uq[4 * kc * kR12Ld + 16 * cb];
 #pragma unroll
           for (int rb = 0; rb < 4; ++rb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][cb], 0, 0, 0);
         }
