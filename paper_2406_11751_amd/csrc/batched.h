@@ -16,10 +16,50 @@ struct BatchItem {
   int32_t problem, local, count;
 };
 
+// The argument tables are read from device memory, so the compiler cannot
+// tell that their pointers address global memory and would go through flat
+// instructions, which also count against the LDS counter and make it wait for
+// each load before the next.  Each pointer field is therefore re-read from
+// the table as a pointer to global memory.
+template <typename T>
+__device__ __forceinline__ T* global_field(T* const& field) {
+  using G = __attribute__((address_space(1))) T*;
+  return (T*)*static_cast<const G*>(static_cast<const void*>(&field));
+}
+__device__ __forceinline__ void to_global(SketchArgs& a, const SketchArgs& t) {
+  a.A = global_field(t.A);
+  a.As = global_field(t.As);
+  a.tri = global_field(t.tri);
+  a.Rs = global_field(t.Rs);
+  a.idx_out = global_field(t.idx_out);
+  a.As_out = global_field(t.As_out);
+  a.Rs_out = global_field(t.Rs_out);
+}
+__device__ __forceinline__ void to_global(PassAArgs& a, const PassAArgs& t) {
+  a.A = global_field(t.A);
+  a.tri_s = global_field(t.tri_s);
+  a.partials = global_field(t.partials);
+  a.W = global_field(t.W);
+}
+__device__ __forceinline__ void to_global(PassBArgs& a, const PassBArgs& t) {
+  a.T2 = global_field(t.T2);
+  a.Q = global_field(t.Q);
+}
+__device__ __forceinline__ void to_global(CholArgs& a, const CholArgs& t) {
+  a.partial2 = global_field(t.partial2);
+  a.Rs = global_field(t.Rs);
+  a.T2 = global_field(t.T2);
+  a.R = global_field(t.R);
+  a.G1_out = global_field(t.G1_out);
+  a.R2_out = global_field(t.R2_out);
+  a.Gg = global_field(t.Gg);
+}
+
 __global__ __launch_bounds__(kGatherThreads) void kb_gather(const SketchArgs* __restrict__ args,
                                                             const BatchItem* __restrict__ items) {
   const BatchItem it = items[blockIdx.x];
-  const SketchArgs a = args[it.problem];
+  SketchArgs a = args[it.problem];
+  to_global(a, args[it.problem]);
   gather_body(a, it.local);
 }
 
@@ -29,6 +69,7 @@ __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr(const SketchArgs*
   const int p = probs[blockIdx.x];
   SketchArgs a = args[p];
   a.info = info + 2 * p;
+  to_global(a, args[p]);
   sketch_qr_body<RPT>(a);
 }
 
@@ -38,6 +79,7 @@ __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr_wide(const Sketch
   const int p = probs[blockIdx.x];
   SketchArgs a = args[p];
   a.info = info + 2 * p;
+  to_global(a, args[p]);
   sketch_qr_body<RPT, true>(a);
 }
 
@@ -48,6 +90,7 @@ __global__ __launch_bounds__(kSketchThreads) void kb_sketch_qr_generic(const Ske
   const int p = probs[blockIdx.x];
   SketchArgs a = args[p];
   a.info = info + 2 * p;
+  to_global(a, args[p]);
   sketch_qr_generic_body<MAXN>(a);
 }
 
@@ -57,6 +100,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void kb_passA(const PassAArgs* __r
   const BatchItem it = items[blockIdx.x];
   PassAArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
+  to_global(a, args[it.problem]);
   passA_body<NMAX>(a, it.local, it.count);
 }
 
@@ -66,6 +110,7 @@ __global__ __launch_bounds__(kCholThreads, 1) void kb_cholesky(const CholArgs* _
   const int p = probs[blockIdx.x];
   CholArgs a = args[p];
   a.info = info + 2 * p;
+  to_global(a, args[p]);
   cholesky_body<NMAX>(a);
 }
 
@@ -75,6 +120,7 @@ __global__ __launch_bounds__(kPassBThreads) void kb_passB(const PassBArgs* __res
   const BatchItem it = items[blockIdx.x];
   PassBArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
+  to_global(a, args[it.problem]);
   passB_body<NMAX>(a, it.local, it.count);
 }
 
@@ -83,6 +129,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void kb_passW(const PassAArgs* __r
   const BatchItem it = items[blockIdx.x];
   PassAArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
+  to_global(a, args[it.problem]);
   passW_body(a, it.local, it.count);
 }
 
@@ -91,6 +138,7 @@ __global__ __launch_bounds__(kPassThreads) void kb_gramW(const PassAArgs* __rest
   const BatchItem it = items[blockIdx.x];
   PassAArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
+  to_global(a, args[it.problem]);
   gramW_body(a, it.local, it.count);
 }
 
@@ -99,6 +147,7 @@ __global__ __launch_bounds__(kPassB128Threads) void kb_passB128(const PassBArgs*
   const BatchItem it = items[blockIdx.x];
   PassBArgs a = args[it.problem];
   a.info = info + 2 * it.problem;
+  to_global(a, args[it.problem]);
   passB128_body(a, it.local, it.count);
 }
 

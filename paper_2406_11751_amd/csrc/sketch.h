@@ -189,16 +189,19 @@ __device__ __forceinline__ void sketch_qr_body(const SketchArgs& a) {
     if (q == (k & 3)) {
       // Every slot is written (zero outside rows k .. s-1), so that the
       // reflector's readers need no row mask.  In the 128-column kernel the
-      // lane's base address is made opaque so that slot t is an immediate
-      // offset from it: per-slot addresses hoisted out of the step loop spill
-      // there, and their reloads would sit on the step's critical path.
+      // lane's index is made opaque so that slot t is an immediate offset
+      // from one LDS address: per-slot addresses hoisted out of the step loop
+      // spill there, and their reloads would sit on the step's critical path.
+      // (An opaque pointer instead would lose its address space and turn the
+      // LDS stores into flat ones.)
       if constexpr (WIDE) {
-        double* vb = &vbuf[buf][l16];
-        asm volatile("" : "+v"(vb));
+        int li = l16 + 16 * RPT * buf;
+        asm volatile("" : "+v"(li));
+        double* vb = &vbuf[0][0];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
           const int r = l16 + 16 * t;
-          vb[16 * t] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
+          vb[li + 16 * t] = (r >= k && r < s) ? ((r == k) ? 1.0 : W[t] * d) : 0.0;
         }
       } else {
 #pragma unroll
