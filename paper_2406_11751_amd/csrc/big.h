@@ -753,7 +753,7 @@ struct BigGramArgs {
 
 constexpr int kGRows = 32;
 constexpr int kXcds = 8;  // accelerator complex dies of the device, each with its own L2
-constexpr int kGLd = 2 * kBigBlock + 4;  // LDS row stride of the staged strips
+constexpr int kGLd = 2 * kBigBlock + 1;  // LDS row stride of the staged strips (odd: the transposing stores of 32 rows hit distinct banks)
 
 template <bool DIAG, int WV>
 __device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int J, int split, double* xs) {
