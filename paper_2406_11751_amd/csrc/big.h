@@ -67,6 +67,50 @@ __device__ __forceinline__ double slot_value(const double (&W)[RPT], int t) {
 // registers next to the column.
 __device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
 
+// Sum over t of v(t) W[t] as one fma chain in ascending t, v(t) = vb[16 t] in
+// LDS, and the update W[t] -= tt v(t).  The reflector is read in chunks of
+// kVChunk slots, each chunk issued before the products of the previous one
+// (the scheduling barriers keep that order: left to itself the compiler puts
+// each LDS read right before its fma and waits for it there).
+constexpr int kVChunk = 8;
+template <int RPT>
+__device__ __forceinline__ double lds_dot(const double* vb, const double (&W)[RPT]) {
+  static_assert(RPT % kVChunk == 0, "chunks");
+  double v[2][kVChunk];
+#pragma unroll
+  for (int u = 0; u < kVChunk; ++u) v[0][u] = vb[16 * u];
+  double p = 0.0;
+#pragma unroll
+  for (int c = 0; c < RPT / kVChunk; ++c) {
+    if (c + 1 < RPT / kVChunk) {
+#pragma unroll
+      for (int u = 0; u < kVChunk; ++u) v[(c + 1) & 1][u] = vb[16 * (kVChunk * (c + 1) + u)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) p = __builtin_fma(v[c & 1][u], W[kVChunk * c + u], p);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return p;
+}
+template <int RPT>
+__device__ __forceinline__ void lds_update(const double* vb, double tt, double (&W)[RPT]) {
+  double v[2][kVChunk];
+#pragma unroll
+  for (int u = 0; u < kVChunk; ++u) v[0][u] = vb[16 * u];
+#pragma unroll
+  for (int c = 0; c < RPT / kVChunk; ++c) {
+    if (c + 1 < RPT / kVChunk) {
+#pragma unroll
+      for (int u = 0; u < kVChunk; ++u) v[(c + 1) & 1][u] = vb[16 * (kVChunk * (c + 1) + u)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) W[kVChunk * c + u] = __builtin_fma(-tt, v[c & 1][u], W[kVChunk * c + u]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <int RPT>
 __global__ __launch_bounds__(16 * panel_width<RPT>()) void k_sketch_panel(BigSketchArgs a) {
   constexpr int PW = panel_width<RPT>(), NT = 16 * PW;
@@ -133,13 +177,9 @@ __global__ __launch_bounds__(16 * panel_width<RPT>()) void k_sketch_panel(BigSke
   auto apply = [&](int k) __attribute__((always_inline)) {
     const int buf = k & 1;
     const double tau = tau_s[buf];
-    double p = 0.0;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) p = __builtin_fma(vbuf[buf][l16 + 16 * t], W[t], p);
-    const double tt = tau * row16_sum(p);
+    const double tt = tau * row16_sum(lds_dot<RPT>(&vbuf[buf][l16], W));
     lds_reload_point();
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vbuf[buf][l16 + 16 * t], W[t]);
+    lds_update<RPT>(&vbuf[buf][l16], tt, W);
     if (l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = slot_value(W, k >> 4);
   };
 
@@ -202,13 +242,9 @@ __global__ __launch_bounds__(kTrailThreads) void k_sketch_trail(BigSketchArgs a)
     const int buf = (k - c0) & 1;
     fetch(k + 1);
     const double tau = a.tau[k];
-    double p = 0.0;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) p = __builtin_fma(vbuf[buf][l16 + 16 * t], W[t], p);
-    const double tt = tau * row16_sum(p);
+    const double tt = tau * row16_sum(lds_dot<RPT>(&vbuf[buf][l16], W));
     lds_reload_point();
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) W[t] = __builtin_fma(-tt, vbuf[buf][l16 + 16 * t], W[t]);
+    lds_update<RPT>(&vbuf[buf][l16], tt, W);
     if (j < n && l16 == (k & 15)) a.Rg[(int64_t)k * n + j] = slot_value(W, k >> 4);
     put(buf ^ 1);  // read in step k+1, after the barrier; last read in step k-1
     __syncthreads();
