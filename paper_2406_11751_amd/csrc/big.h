@@ -74,12 +74,11 @@ __device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory
 // each LDS read right before its fma and waits for it there).
 constexpr int kVChunk = 8;
 template <int RPT>
-__device__ __forceinline__ double lds_dot(const double* vb, const double (&W)[RPT]) {
+__device__ __forceinline__ double lds_dot(const double* vb, const double (&W)[RPT], double p = 0.0) {
   static_assert(RPT % kVChunk == 0, "chunks");
   double v[2][kVChunk];
 #pragma unroll
   for (int u = 0; u < kVChunk; ++u) v[0][u] = vb[16 * u];
-  double p = 0.0;
 #pragma unroll
   for (int c = 0; c < RPT / kVChunk; ++c) {
     if (c + 1 < RPT / kVChunk) {
@@ -92,6 +91,36 @@ __device__ __forceinline__ double lds_dot(const double* vb, const double (&W)[RP
     __builtin_amdgcn_sched_barrier(0);
   }
   return p;
+}
+// The same with one chunk in flight at a time (its reads, then its products):
+// fewer registers, for the kernels that have none to spare.
+template <int RPT>
+__device__ __forceinline__ double lds_dot1(const double* vb, const double (&W)[RPT], double p) {
+  static_assert(RPT % kVChunk == 0, "chunks");
+#pragma unroll
+  for (int c = 0; c < RPT / kVChunk; ++c) {
+    double v[kVChunk];
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) v[u] = vb[16 * (kVChunk * c + u)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) p = __builtin_fma(v[u], W[kVChunk * c + u], p);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return p;
+}
+template <int RPT>
+__device__ __forceinline__ void lds_update1(const double* vb, double tt, double (&W)[RPT]) {
+#pragma unroll
+  for (int c = 0; c < RPT / kVChunk; ++c) {
+    double v[kVChunk];
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) v[u] = vb[16 * (kVChunk * c + u)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kVChunk; ++u) W[kVChunk * c + u] = __builtin_fma(-tt, v[u], W[kVChunk * c + u]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 template <int RPT>
 __device__ __forceinline__ void lds_update(const double* vb, double tt, double (&W)[RPT]) {
@@ -486,13 +515,23 @@ template <int L>
 __device__ __forceinline__ void w_apply(double (&W)[L], const double* v, double tau, int lane, int k0, int k1,
                                         double& keep0, double& keep1) {
   const int g = lane >> 4, p = lane & 15;
-  const double tt = tau * w_chain<L>(lane, [&](int i, double acc) __attribute__((always_inline)) {
-    return __builtin_fma(v[p + 16 * (g * L + i)], W[i], acc);
-  });
+  // this lane's slots of v: v(p + 16 (g L + i)) at vb[16 i]; the chain of each
+  // lane row reads them a chunk at a time (lds_dot1)
+  const double* vb = v + p + 16 * g * L;
+  double acc = 0.0;
+#pragma unroll
+  for (int gg = 0; gg < 4; ++gg) {
+    if (g == gg) acc = lds_dot1<L>(vb, W, acc);
+    if (gg < 3) {
+      const double up = from_row_above(acc, lane);
+      if (g == gg + 1) acc = up;
+    }
+  }
+  const double tt = tau * readlane_d(row16_sum(acc), 48);
+  lds_update1<L>(vb, tt, W);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int r = p + 16 * (g * L + i);
-    W[i] = __builtin_fma(-tt, v[r], W[i]);
     keep0 = (r == k0) ? W[i] : keep0;
     keep1 = (r == k1) ? W[i] : keep1;
   }

@@ -11,6 +11,8 @@ checked on the gfx950 assembly (hipcc cross-compiles without a GPU):
   a wait for the loads in flight, which turns a prefetch into one load at a
   time.  The sign in the assembly is a load, `s_waitcnt vmcnt(0)`, then the
   next load.
+- The Householder sweeps of the sketch for n > 128 read the reflector from LDS
+  a chunk at a time, not one read and one wait per fma.
 """
 import os
 import re
@@ -77,3 +79,24 @@ def test_large_n_prefetches_are_not_serialized(asm):
     # per block; the A1 prefetch in the k-chunk loop must stay pipelined
     assert serialized_loads(trsm) <= 8
     assert re.search(r"s_waitcnt vmcnt\((8|9|10|11)\)", trsm)
+
+
+def lds_reads_waited_one_by_one(body):
+    ev = []
+    for line in body.split("\n"):
+        line = line.strip()
+        if line.startswith("ds_read"):
+            ev.append("R")
+        elif line.startswith("s_waitcnt") and "lgkmcnt(0)" in line:
+            ev.append("W")
+        elif line.startswith("s_waitcnt"):
+            ev.append("w")
+    return sum(1 for i in range(len(ev) - 1) if ev[i] == "R" and ev[i + 1] == "W")
+
+
+def test_large_n_sketch_reads_the_reflector_in_chunks(asm):
+    ks = kernels(asm, r"k_sketch_(panel|trail)(_w)?ILi")
+    assert len(ks) == 18  # RPT = 16 ... 96 and L = 32, 64, 96, panel and trail each
+    for name, body in ks.items():
+        reads = len(re.findall(r"\n\s+ds_read", body))
+        assert lds_reads_waited_one_by_one(body) <= max(8, reads // 16), name
