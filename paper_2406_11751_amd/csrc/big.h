@@ -780,13 +780,17 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) b[rb] = ring[kc % kDepth][rb];
         fetch_b(16 * Qb + kc + kDepth, ring[kc % kDepth]);
+        // the chunk's four U operands read together (one LDS wait, not four);
+        // -U: fma(-u, b, acc) rounds as fma(u, -b, acc), the update -A1(:, k) U(k, :)
+        double u[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          // -U: fma(-u, b, acc) rounds as fma(u, -b, acc), the update -A1(:, k) U(k, :)
-          const double u = -uq[4 * kc * kR12Ld + 16 * cb];
+        for (int cb = 0; cb < 4; ++cb) u[cb] = uq[4 * kc * kR12Ld + 16 * cb];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int rb = 0; rb < 4; ++rb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u, b[rb], acc[rb][cb], 0, 0, 0);
-        }
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-u[cb], b[rb], acc[rb][cb], 0, 0, 0);
       }
       __syncthreads();
     }
