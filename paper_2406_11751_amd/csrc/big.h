@@ -834,21 +834,29 @@ constexpr int kGRows = 32;
 constexpr int kXcds = 8;  // accelerator complex dies of the device, each with its own L2
 constexpr int kGLd = 2 * kBigBlock + 1;  // LDS row stride of the staged strips (odd: the transposing stores of 32 rows hit distinct banks)
 
-template <bool DIAG, int WV>
+// Group kinds: kGramOff, the pair I < J of 128-column blocks (G(I, J), 64
+// tiles); kGramDiag, one diagonal block (G(I, I), 36 upper tiles); kGramDiag2,
+// two diagonal blocks I and J = I + 1 (72 tiles, about the work of an
+// off-diagonal group, so that the groups of one row split go through the rows
+// at the same pace and share them in L2).  Wave WV takes tile rows
+// {2 WV, 2 WV + 1} of G(I, J), or rows {WV, 7 - WV} of each diagonal block.
+constexpr int kGramOff = 0, kGramDiag = 1, kGramDiag2 = 2;
+
+template <int MODE, int WV>
 __device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int J, int split, double* xs) {
-  constexpr int NTW = DIAG ? 9 : 16;  // tiles of this wave
-  // tile rows of this wave and the first tile column of each
-  constexpr int B0 = DIAG ? WV : 2 * WV, B1 = DIAG ? 7 - WV : 2 * WV + 1;
-  constexpr int C0 = DIAG ? B0 : 0, C1 = DIAG ? B1 : 0;
-  constexpr int N0 = 8 - C0;  // tiles in row B0
-  static_assert(N0 + (8 - C1) == NTW, "tile count");
+  constexpr int NSET = MODE == kGramDiag2 ? 2 : 1;
+  constexpr int NTS = MODE == kGramOff ? 16 : 9;  // tiles per set
+  constexpr int NTW = NSET * NTS;                  // tiles of this wave
+  // tile rows of this wave in a set and the first tile column of each
+  constexpr int B0 = MODE == kGramOff ? 2 * WV : WV, B1 = MODE == kGramOff ? 2 * WV + 1 : 7 - WV;
+  constexpr int C0 = MODE == kGramOff ? 0 : B0, C1 = MODE == kGramOff ? 0 : B1;
+  static_assert((8 - C0) + (8 - C1) == NTS, "tile count");
   const int lane = threadIdx.x & (kWave - 1);
   const int rq = lane >> 4, cq = lane & 15;
-  const int joff = DIAG ? 0 : kBigBlock;  // column offset of the J strip in LDS
   d4 acc[NTW];
 #pragma unroll
   for (int i = 0; i < NTW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  constexpr int STRIP = DIAG ? kBigBlock : 2 * kBigBlock;
+  constexpr int STRIP = MODE == kGramDiag ? kBigBlock : 2 * kBigBlock;
   constexpr int U = kGRows * STRIP / kPassThreads;  // staged values per thread
   const int64_t blocks = (a.m + kGRows - 1) / kGRows;
   const int nsplit = a.nsplit;
@@ -878,20 +886,27 @@ __device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int 
 #pragma unroll
     for (int qq = 0; qq < kGRows / 4; ++qq) {
       const double* xr = xs + (4 * qq + rq) * kGLd;
-      const double a0 = xr[16 * B0 + cq], a1 = xr[16 * B1 + cq];
-      double bv[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) bv[c] = xr[joff + 16 * c + cq];
-      int tt = 0;
+      for (int set = 0; set < NSET; ++set) {
+        // A operand rows from the first strip of the set, B operand columns
+        // from the second (the same strip for a diagonal block)
+        const int aoff = set * kBigBlock;
+        const int boff = MODE == kGramOff ? kBigBlock : set * kBigBlock;
+        const double a0 = xr[aoff + 16 * B0 + cq], a1 = xr[aoff + 16 * B1 + cq];
+        double bv[8];
 #pragma unroll
-      for (int c = C0; c < 8; ++c) {
-        acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[c], acc[tt], 0, 0, 0);
-        ++tt;
-      }
+        for (int c = 0; c < 8; ++c) bv[c] = xr[boff + 16 * c + cq];
+        int tt = set * NTS;
 #pragma unroll
-      for (int c = C1; c < 8; ++c) {
-        acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[c], acc[tt], 0, 0, 0);
-        ++tt;
+        for (int c = C0; c < 8; ++c) {
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[c], acc[tt], 0, 0, 0);
+          ++tt;
+        }
+#pragma unroll
+        for (int c = C1; c < 8; ++c) {
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[c], acc[tt], 0, 0, 0);
+          ++tt;
+        }
       }
     }
   }
@@ -900,15 +915,20 @@ __device__ __forceinline__ void gram_big_tiles(const BigGramArgs& a, int I, int 
   double* out = a.partials + (int64_t)split * a.E;
   int tt = 0;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int bi = 8 * I + (h == 0 ? B0 : B1);
+  for (int set = 0; set < NSET; ++set) {
+    const int RI = set == 0 ? I : J;                              // block row of the set
+    const int RJ = MODE == kGramOff ? J : (set == 0 ? I : J);    // block column
 #pragma unroll
-    for (int c = (h == 0 ? C0 : C1); c < 8; ++c) {
-      const int bj = 8 * J + c;
-      const int tile = bi * NB - bi * (bi - 1) / 2 + (bj - bi);
+    for (int h = 0; h < 2; ++h) {
+      const int bi = 8 * RI + (h == 0 ? B0 : B1);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(int64_t)tile * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[tt][v];
-      ++tt;
+      for (int c = (h == 0 ? C0 : C1); c < 8; ++c) {
+        const int bj = 8 * RJ + c;
+        const int tile = bi * NB - bi * (bi - 1) / 2 + (bj - bi);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(int64_t)tile * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[tt][v];
+        ++tt;
+      }
     }
   }
 }
@@ -929,29 +949,42 @@ __global__ __launch_bounds__(kPassThreads) void k_gram_big(BigGramArgs a) {
     gi = blockIdx.x % a.ngroups;
     split = blockIdx.x / a.ngroups;
   }
+  // Group gi: the off-diagonal pairs I < J first (row by row), then the
+  // diagonal blocks two at a time, the last alone when their number is odd.
   const int NG = a.nmax / kBigBlock;
-  int I = 0, rem = gi;
-  while (rem >= NG - I) {
-    rem -= NG - I;
-    ++I;
-  }
-  const int J = I + rem;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (I == J) {
-    switch (wv) {
-      case 0: gram_big_tiles<true, 0>(a, I, J, split, xs); break;
-      case 1: gram_big_tiles<true, 1>(a, I, J, split, xs); break;
-      case 2: gram_big_tiles<true, 2>(a, I, J, split, xs); break;
-      default: gram_big_tiles<true, 3>(a, I, J, split, xs); break;
+  const int noff = NG * (NG - 1) / 2;
+  int mode, I, J;
+  if (gi < noff) {
+    mode = kGramOff;
+    I = 0;
+    int rem = gi;
+    while (rem >= NG - 1 - I) {
+      rem -= NG - 1 - I;
+      ++I;
     }
+    J = I + 1 + rem;
   } else {
-    switch (wv) {
-      case 0: gram_big_tiles<false, 0>(a, I, J, split, xs); break;
-      case 1: gram_big_tiles<false, 1>(a, I, J, split, xs); break;
-      case 2: gram_big_tiles<false, 2>(a, I, J, split, xs); break;
-      default: gram_big_tiles<false, 3>(a, I, J, split, xs); break;
-    }
+    I = 2 * (gi - noff);
+    J = I + 1;
+    mode = J < NG ? kGramDiag2 : kGramDiag;
+    if (mode == kGramDiag) J = I;
   }
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#define RPQ_GRAM_WAVES(M)                                       \
+  switch (wv) {                                                 \
+    case 0: gram_big_tiles<M, 0>(a, I, J, split, xs); break;    \
+    case 1: gram_big_tiles<M, 1>(a, I, J, split, xs); break;    \
+    case 2: gram_big_tiles<M, 2>(a, I, J, split, xs); break;    \
+    default: gram_big_tiles<M, 3>(a, I, J, split, xs); break;   \
+  }
+  if (mode == kGramOff) {
+    RPQ_GRAM_WAVES(kGramOff)
+  } else if (mode == kGramDiag2) {
+    RPQ_GRAM_WAVES(kGramDiag2)
+  } else {
+    RPQ_GRAM_WAVES(kGramDiag)
+  }
+#undef RPQ_GRAM_WAVES
 }
 
 // Line 6: Q = A1 R2^{-1} with the explicit inverse T2 (nmax x nmax row-major,

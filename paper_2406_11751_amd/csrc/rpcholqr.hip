@@ -123,7 +123,7 @@ bool make_big_plan(int64_t m, int64_t n, int64_t s, BigPlan* p, int64_t pa_cap =
   const int64_t wl = (rows + 3) / 4;
   p->wl = p->rpt > 0 ? 0 : wl <= 32 ? 32 : wl <= 64 ? 64 : wl <= 96 ? 96 : 0;
   const int ng = p->nmax / kBigBlock;
-  p->ngroups = ng * (ng + 1) / 2;
+  p->ngroups = ng * (ng - 1) / 2 + (ng + 1) / 2;  // k_gram_big groups: off-diagonal pairs, diagonal pairs
   const int64_t rblocks = (m + kGRows - 1) / kGRows;
   int64_t ns = (1024 + p->ngroups - 1) / p->ngroups;
   ns = std::min<int64_t>(std::min<int64_t>(ns, rblocks), std::min<int64_t>(pa_cap, kPassAMaxBlocks));
