@@ -717,13 +717,16 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
   const int nit = 16 * P;  // k-chunks of the update
   const int64_t panels = (a.m + kWave - 1) / kWave;
   const int64_t pgroups = (panels + kPassWaves - 1) / kPassWaves;
-  // U(64 Qb .., 64 P ..) into LDS buffer buf
+  // -U(64 Qb .., 64 P ..) into LDS buffer buf.  The negation is taken here, once
+  // per element, rather than on the MFMA operand each time it is read
+  // (fma(-u, b, acc) is the update -A1(:, k) U(k, :) and rounds as
+  // fma(u, -b, acc)).
   auto load_u = [&](int Qb, int buf) __attribute__((always_inline)) {
     const double* src = a.full + (int64_t)(kWH * Qb) * a.nmax + c0;
 #pragma unroll 4
     for (int u = 0; u < RPT; ++u) {
       const int e = threadIdx.x + u * kPassThreads;
-      rq[buf][(e / kWH) * kR12Ld + e % kWH] = src[(int64_t)(e / kWH) * a.nmax + e % kWH];
+      rq[buf][(e / kWH) * kR12Ld + e % kWH] = -src[(int64_t)(e / kWH) * a.nmax + e % kWH];
     }
   };
   for (int64_t pg = blockIdx.x; pg < pgroups; pg += gridDim.x) {
@@ -780,8 +783,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) b[rb] = ring[kc % kDepth][rb];
         fetch_b(16 * Qb + kc + kDepth, ring[kc % kDepth]);
-        // the chunk's four U operands read together (one LDS wait, not four);
-        // -U: fma(-u, b, acc) rounds as fma(u, -b, acc), the update -A1(:, k) U(k, :)
+        // the chunk's four -U operands read together (one LDS wait, not four)
         double u[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) u[cb] = uq[4 * kc * kR12Ld + 16 * cb];
@@ -790,7 +792,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
         for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
           for (int rb = 0; rb < 4; ++rb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-u[cb], b[rb], acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[cb], b[rb], acc[rb][cb], 0, 0, 0);
       }
       __syncthreads();
     }

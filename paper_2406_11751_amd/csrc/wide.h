@@ -93,8 +93,10 @@ __device__ __forceinline__ void transpose_sets(double (&vals)[4][16]) {
 __device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk) {
   __shared__ double r12s[kWH * kR12Ld];
   if (a.info[0] != 0) return;
+  // -R12 in LDS: the update A(:, 64:) - A1(:, :64) R12 takes fma(-r, x, acc),
+  // which rounds as fma(r, -x, acc), with no negation of an MFMA operand
   for (int e = threadIdx.x; e < kWH * kWH; e += kPassThreads)
-    r12s[(e / kWH) * kR12Ld + e % kWH] = a.tri_s[2 * kWideTri + e];
+    r12s[(e / kWH) * kR12Ld + e % kWH] = -a.tri_s[2 * kWideTri + e];
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g = lane >> 4;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void passW_body(const PassAArgs& a, int bid, int nblk
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(r12s[(4 * c + g) * kR12Ld + 16 * cb + i16], -vals[rb][c],
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(r12s[(4 * c + g) * kR12Ld + 16 * cb + i16], vals[rb][c],
                                                          acc[cb], 0, 0, 0);
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
