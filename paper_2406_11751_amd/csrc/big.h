@@ -783,7 +783,10 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) b[rb] = ring[kc % kDepth][rb];
         fetch_b(16 * Qb + kc + kDepth, ring[kc % kDepth]);
-        // the chunk's four -U operands read together (one LDS wait, not four)
+        // the chunk's four -U operands read together (one LDS wait, not four);
+        // the wave takes issue priority over the other wave of its SIMD for the
+        // products, which that wave's loads then overlap
+        __builtin_amdgcn_s_setprio(1);
         double u[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) u[cb] = uq[4 * kc * kR12Ld + 16 * cb];
@@ -793,6 +796,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_trsm_panel(BigTrsmArgs a) {
 #pragma unroll
           for (int rb = 0; rb < 4; ++rb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[cb], b[rb], acc[rb][cb], 0, 0, 0);
+        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
     }
@@ -1096,6 +1100,7 @@ __global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs 
 #pragma unroll
           for (int i = 0; i < PERW; ++i) acc[rb][i] = d4{0.0, 0.0, 0.0, 0.0};
       }
+      __builtin_amdgcn_s_setprio(1);  // issue priority for the stage's products
       if (SR * (st + 1) > n) {  // the last stage: columns past n (clamped reads) are zero
 #pragma unroll
         for (int kk = 0; kk < SK; ++kk)
@@ -1116,6 +1121,7 @@ __global__ __launch_bounds__(64 * kPassBBigWaves, 1) void k_passB_big(PassBArgs 
           }
         }
       }
+      __builtin_amdgcn_s_setprio(0);
       // the slot is free again: it takes the stage D - 1 stages after the next
       fetch(j, grp_f, st_f);
       advance(grp_f, st_f);
